@@ -1,0 +1,180 @@
+/*
+ * mclbm.h -- C ABI of the two-component D3Q19 pseudopotential lattice
+ * Boltzmann step for MI355X (gfx950).
+ *
+ * The method is the improved multi-component pseudopotential LBM of
+ * Sedahmed et al., Phys. Fluids 34 (2022), arXiv 2207.01534, Sec. 2:
+ *   forced SRT lattice Boltzmann equation            Eq. (1)
+ *   second-order equilibrium on the common velocity  Eq. (2)
+ *   densities, velocities, mixture density           Eqs. (3)-(5)
+ *   mixture relaxation time from viscosities         Eqs. (6)-(7)
+ *   common equilibrium velocity                      Eq. (8)
+ *   forcing source                                   Eq. (9)
+ *   total, inter-component and fluid-solid forces    Eqs. (10), (11), (13)
+ *   IVSD solid pseudopotential and virtual density   Eqs. (14)-(15)
+ *   pressure                                         Eq. (12)
+ *   halfway bounce-back at fluid-solid interfaces    Secs. 3.2, 4.1
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: nx * ny * nz nodes, node index idx = x + nx*(y + ny*z) (x fastest),
+ * periodic in all three directions; walls are made of solid voxels.
+ * Component 1 is sigma = 0 in arrays, component 2 is sigma = 1.
+ * Lattice units throughout (dx = dt = 1).
+ *
+ * Memory ownership: the caller allocates and owns ALL device memory -- the
+ * workspace handed to mclbm_create, every input, output, saved state,
+ * adjoint buffer and gradient.  The library never allocates or frees device
+ * memory.  It owns only the small host-side handle, released by
+ * mclbm_destroy.  "Device pointer" below means memory of the device that was
+ * current when mclbm_create was called.
+ *
+ * Streams: all device work is enqueued, in order, on the stream given to
+ * mclbm_create (a hipStream_t passed as void*; NULL = the default stream).
+ * Only mclbm_set_geometry, mclbm_diagnostics and mclbm_loss synchronise that
+ * stream, because they return host values.  Calls on one handle must not
+ * overlap from several threads.
+ *
+ * Errors: every call returns an mclbm_status.  MCLBM_EINVAL leaves the
+ * handle unchanged.  HIP failures return MCLBM_EHIP; mclbm_last_error()
+ * gives a thread-local description of the most recent failure.
+ */
+#ifndef MCLBM_H
+#define MCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCLBM_ABI_VERSION 1u
+
+typedef enum {
+    MCLBM_OK = 0,
+    MCLBM_EINVAL = -1,      /* bad argument; nothing was changed            */
+    MCLBM_EHIP = -2,        /* a HIP runtime call failed                      */
+    MCLBM_ENONFINITE = -3,  /* diagnostics found a non-finite population      */
+    MCLBM_ESTATE = -4,      /* call out of order (e.g. step before geometry)  */
+    MCLBM_EVERSION = -5     /* params.abi_version != MCLBM_ABI_VERSION        */
+} mclbm_status;
+
+/* Storage of the populations between steps.  Arithmetic is FP32 in all
+ * three; FP64 is used only in the mass / saturation / loss reductions.
+ *   MCLBM_F32   38 FP32 values per node.
+ *   MCLBM_F16   the 36 moving populations stored in FP16 as offsets from the
+ *               lattice weight of the density-normalised population,
+ *               q_i = f_i / rho_src - w_i, where rho_src is the density of
+ *               the node that wrote the value one step earlier; the two rest
+ *               populations stay FP32 and absorb the rounding residual of the
+ *               node's moving populations, so component mass is conserved to
+ *               FP32 round-off.
+ *   MCLBM_BF16  as MCLBM_F16 with BF16 rounding. */
+typedef enum { MCLBM_F32 = 0, MCLBM_F16 = 1, MCLBM_BF16 = 2 } mclbm_storage;
+
+typedef struct {
+    uint32_t abi_version; /* must equal MCLBM_ABI_VERSION                         */
+    int32_t nx, ny, nz;   /* lattice extents, each >= 3, nx*ny*nz < 2^31          */
+    int32_t storage;      /* mclbm_storage                                        */
+    int32_t reserved;     /* must be 0                                            */
+    double tau[2];        /* relaxation times tau^(1), tau^(2) > 0.5 (Eqs. 6-7)   */
+    double G;             /* cohesion / adhesion strength G_coh (Eqs. 11, 13)     */
+    double g[2][3];       /* body acceleration per component: F^b = rho g (Eq. 10) */
+} mclbm_params;
+
+typedef struct mclbm_lattice mclbm_lattice; /* opaque host-side handle */
+
+/* Version of the library binary (compare with MCLBM_ABI_VERSION). */
+uint32_t mclbm_abi_version(void);
+
+/* Bytes of device workspace mclbm_create needs for these parameters.
+ * EINVAL on invalid parameters. */
+mclbm_status mclbm_workspace_bytes(const mclbm_params* params, size_t* bytes);
+
+/* Create a lattice in the caller's device workspace (>= workspace_bytes,
+ * 256-byte aligned, kept alive and untouched until mclbm_destroy).
+ * stream: hipStream_t for all later work.  *out receives the handle. */
+mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t bytes,
+                          void* stream, mclbm_lattice** out);
+
+/* Geometry and wettability (Eqs. 13-15).
+ * d_solid: uint8[N], nonzero = solid voxel (phi = 1).
+ * d_xi:    float[N], adhesion parameter xi per voxel, read only at solid
+ *          voxels that have a fluid neighbour; chi^(1) = 1 + xi,
+ *          chi^(2) = 1 - xi.  |xi| < 1 required there (EINVAL otherwise).
+ * Both are copied into the workspace; the caller may free them afterwards.
+ * Synchronises the stream.  Resets the step counter to 0. */
+mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, const float* d_xi);
+
+/* Number of solid voxels with at least one fluid neighbour (the voxels whose
+ * xi matters and where gradients are non-zero).  Valid after set_geometry. */
+mclbm_status mclbm_boundary_count(const mclbm_lattice* lat, int64_t* count);
+
+/* Initial state f_i^(sigma) = w_i rho^(sigma) (fluid at rest).
+ * d_rho: float[2][N] (component-major); values at solid voxels are ignored.
+ * Resets the step counter to 0. */
+mclbm_status mclbm_init_equilibrium(mclbm_lattice* lat, const float* d_rho);
+
+/* Advance nsteps >= 0 time steps (Eq. 1: collide with Eqs. 2, 6-11, 13-15,
+ * then stream with halfway bounce-back).  Asynchronous on the stream. */
+mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps);
+
+/* Completed steps since the last init / set_geometry / load_state. */
+mclbm_status mclbm_get_time(const mclbm_lattice* lat, int64_t* t);
+
+/* Readouts of the state at the current time level (pre-collision).
+ * Each output is a caller device buffer; 0 is written at solid voxels.
+ *   density  float[2][N]     rho^(sigma), Eq. (3)
+ *   velocity float[3][N]     common velocity u = u^eq including the
+ *                            half-force shift, Eq. (8)
+ *   force    float[2][3][N]  F^(sigma),tot, Eq. (10)
+ *   pressure float[N]        Eq. (12) */
+mclbm_status mclbm_read_density(mclbm_lattice* lat, float* d_rho);
+mclbm_status mclbm_read_velocity(mclbm_lattice* lat, float* d_u);
+mclbm_status mclbm_read_force(mclbm_lattice* lat, float* d_F);
+mclbm_status mclbm_read_pressure(mclbm_lattice* lat, float* d_P);
+
+/* Diagnostics of the current state, reduced in FP64, copied to the host
+ * (synchronises the stream):
+ *   h_out[0], h_out[1]  component masses over fluid voxels
+ *   h_out[2]            water saturation S_w (Sec. 4.1): fraction of fluid
+ *                       voxels with rho^(2) > rho^(1)
+ *   h_out[3]            smooth non-wetting fraction, mean rho1/(rho1+rho2)
+ *   h_out[4]            max |u| over fluid voxels
+ *   h_out[5]            number of non-finite values among rho, u at fluid voxels
+ *   h_out[6]            number of fluid voxels
+ * Returns MCLBM_ENONFINITE (after filling h_out) if h_out[5] > 0. */
+mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]);
+
+/* Checkpoint / restore of the full state (populations, the density field
+ * the FP16/BF16 codecs decode against, and the step counter).
+ * d_dst / d_src: device buffers of mclbm_state_bytes bytes, 256-byte
+ * aligned.  Restoring reproduces later steps bit for bit. */
+mclbm_status mclbm_state_bytes(const mclbm_lattice* lat, size_t* bytes);
+mclbm_status mclbm_save_state(mclbm_lattice* lat, void* d_dst);
+mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src);
+
+/* Per-kernel timing of mclbm_step with HIP events recorded on the lattice's
+ * stream around each launch (measurement support; two event records per
+ * launch while enabled, no device memory).
+ *   mclbm_profile(lat, 1) clears earlier records and starts collecting;
+ *   mclbm_profile(lat, 0) stops.
+ *   mclbm_profile_read synchronises the stream and returns, for the three
+ *   kernels of a step {0: densities (Eq. 3), 1: virtual solid densities
+ *   (Eqs. 14-15), 2: forces + collision + streaming (Eqs. 1-2, 6-11, 13)},
+ *   the summed durations in milliseconds and the number of launches timed. */
+mclbm_status mclbm_profile(mclbm_lattice* lat, int32_t enable);
+mclbm_status mclbm_profile_read(mclbm_lattice* lat, double h_ms[3], int64_t h_launches[3]);
+
+/* Destroy the handle (the workspace is the caller's to free afterwards). */
+void mclbm_destroy(mclbm_lattice* lat);
+
+const char* mclbm_status_string(mclbm_status s);
+const char* mclbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCLBM_H */

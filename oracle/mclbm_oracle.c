@@ -52,6 +52,9 @@
 #include <stddef.h>
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
 #define NC 2
@@ -426,4 +429,14 @@ double orc_loss_snw(const orc_params *p, const uint8_t *solid, const uint8_t *re
         cnt += 1.0;
     }
     return cnt > 0 ? acc / cnt : 0.0;
+}
+
+/* Number of OpenMP threads the lattice-wide loops use (1 without OpenMP). */
+int32_t orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -58,6 +58,7 @@ def _lib():
         lib.orc_diagnostics.argtypes = [P, bp, dp, dp, dp, dp]
         lib.orc_loss_snw.argtypes = [P, bp, bp, dp]
         lib.orc_loss_snw.restype = ctypes.c_double
+        lib.orc_num_threads.restype = ctypes.c_int32
         _LIB = lib
     return _LIB
 
@@ -70,6 +71,10 @@ def _d(a):
 def _b(a):
     assert a.dtype == np.uint8 and a.flags.c_contiguous
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def num_threads() -> int:
+    return int(_lib().orc_num_threads())
 
 
 def lattice_tables():

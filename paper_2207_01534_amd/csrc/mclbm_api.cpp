@@ -1,0 +1,431 @@
+// C ABI of the two-component D3Q19 step (declared in include/mclbm.h):
+// parameter validation, workspace carving and launch sequencing on the
+// caller's stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mclbm.h"
+#include "lbm_kernels.hpp"
+
+using namespace mclbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mclbm_status fail(mclbm_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(MCLBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int storage) { return storage == MCLBM_F32 ? 4 : 2; }
+
+struct Layout {
+    size_t mv, rest, R0, R1, nbm, list, xil, counts, bad, partial, misc, total;
+    size_t mv_bytes, rest_bytes, r_bytes;
+    int np;
+};
+
+Layout make_layout(const mclbm_params& p) {
+    Layout L{};
+    const size_t n = (size_t)p.nx * p.ny * p.nz;
+    // plane stride: padded and skewed by 256 elements so that the 38 streams
+    // do not start on the same HBM channel when n is a power of two
+    L.np = (int)align_up(n + 256, 256);
+    const Geo g{p.nx, p.ny, p.nz, (int)n, L.np};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, kAlign);
+        return at;
+    };
+    L.mv_bytes = (size_t)(2 * (Q - 1)) * L.np * elem_bytes(p.storage);
+    L.rest_bytes = (size_t)2 * L.np * sizeof(float);
+    L.r_bytes = n * sizeof(float2);
+    L.mv = take(L.mv_bytes);
+    L.rest = take(L.rest_bytes);
+    L.R0 = take(L.r_bytes);
+    L.R1 = take(L.r_bytes);
+    L.nbm = take(n * sizeof(uint32_t));
+    L.list = take(n * sizeof(int));
+    L.xil = take(n * sizeof(float));
+    L.counts = take((size_t)boundary_blocks(g) * sizeof(int));
+    L.bad = take((size_t)boundary_blocks(g) * sizeof(int));
+    L.partial = take((size_t)fields_blocks(g) * 8 * sizeof(double));
+    L.misc = take(256);
+    L.total = off;
+    return L;
+}
+
+mclbm_status check_params(const mclbm_params* p) {
+    if (!p) return fail(MCLBM_EINVAL, "params is NULL");
+    if (p->abi_version != MCLBM_ABI_VERSION) return fail(MCLBM_EVERSION, "abi_version mismatch");
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail(MCLBM_EINVAL, "extents must be >= 3");
+    const double n = (double)p->nx * p->ny * p->nz;
+    if (n + 512 >= 2147483647.0) return fail(MCLBM_EINVAL, "nx*ny*nz must be < 2^31");
+    if (p->storage < MCLBM_F32 || p->storage > MCLBM_BF16) return fail(MCLBM_EINVAL, "bad storage");
+    if (p->reserved != 0) return fail(MCLBM_EINVAL, "reserved must be 0");
+    for (int s = 0; s < 2; ++s) {
+        if (!(p->tau[s] > 0.5) || !std::isfinite(p->tau[s]))
+            return fail(MCLBM_EINVAL, "tau must be finite and > 0.5");
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(p->g[s][a])) return fail(MCLBM_EINVAL, "g must be finite");
+    }
+    if (!std::isfinite(p->G)) return fail(MCLBM_EINVAL, "G must be finite");
+    return MCLBM_OK;
+}
+
+}  // namespace
+
+struct mclbm_lattice {
+    mclbm_params p;
+    Geo g;
+    Phys ph;
+    CollideLaunch cl;
+    Layout L;
+    hipStream_t stream;
+    char* ws;
+    int64_t t;
+    int nbound;
+    bool geometry;
+    bool initialized;
+    // per-kernel event pairs recorded by mclbm_step while profiling
+    bool profiling = false;
+    std::vector<hipEvent_t> ev[3];
+
+    float2* R(int k) const { return (float2*)(ws + (k ? L.R1 : L.R0)); }
+    uint32_t* nbm() const { return (uint32_t*)(ws + L.nbm); }
+    int* list() const { return (int*)(ws + L.list); }
+    float* xil() const { return (float*)(ws + L.xil); }
+    double* partial() const { return (double*)(ws + L.partial); }
+    int* misc_int() const { return (int*)(ws + L.misc); }
+    double* diag_out() const { return (double*)(ws + L.misc + 64); }
+
+    template <class C>
+    Pops<C> pops() const {
+        return Pops<C>{(typename C::T*)(ws + L.mv), (float*)(ws + L.rest)};
+    }
+    template <class F>
+    void with_codec(F&& fn) const {
+        if (p.storage == MCLBM_F16)
+            fn(CodecF16{});
+        else if (p.storage == MCLBM_BF16)
+            fn(CodecBF16{});
+        else
+            fn(CodecF32{});
+    }
+    // psi-hat of the current time level in R[t & 1]
+    void fill_psi() {
+        const int odd = (int)(t & 1);
+        float2* psi = R((int)(t & 1));
+        const float2* rprev = R((int)((t + 1) & 1));
+        with_codec([&](auto c) {
+            using C = decltype(c);
+            launch_density<C>(pops<C>(), nbm(), rprev, psi, g, odd, stream);
+        });
+        launch_ivsd(list(), xil(), nbound, nbm(), psi, g, stream);
+    }
+    void fields(float* o_rho, float* o_u, float* o_F, float* o_P, double* partial, double* out) {
+        fill_psi();
+        const int odd = (int)(t & 1);
+        const float2* psi = R((int)(t & 1));
+        const float2* rprev = R((int)((t + 1) & 1));
+        with_codec([&](auto c) {
+            using C = decltype(c);
+            launch_fields<C>(pops<C>(), nbm(), rprev, psi, g, ph, odd, o_rho, o_u, o_F, o_P, partial, out,
+                             stream);
+        });
+    }
+};
+
+extern "C" {
+
+uint32_t mclbm_abi_version(void) { return MCLBM_ABI_VERSION; }
+
+mclbm_status mclbm_workspace_bytes(const mclbm_params* params, size_t* bytes) {
+    mclbm_status st = check_params(params);
+    if (st != MCLBM_OK) return st;
+    if (!bytes) return fail(MCLBM_EINVAL, "bytes is NULL");
+    *bytes = make_layout(*params).total;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t bytes, void* stream,
+                          mclbm_lattice** out) {
+    mclbm_status st = check_params(params);
+    if (st != MCLBM_OK) return st;
+    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+    if (!d_workspace) return fail(MCLBM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_workspace) % kAlign) return fail(MCLBM_EINVAL, "workspace must be 256-byte aligned");
+    const Layout L = make_layout(*params);
+    if (bytes < L.total) return fail(MCLBM_EINVAL, "workspace too small");
+    mclbm_lattice* lat = new (std::nothrow) mclbm_lattice();
+    if (!lat) return fail(MCLBM_EINVAL, "out of host memory");
+    lat->p = *params;
+    lat->L = L;
+    lat->g = Geo{params->nx, params->ny, params->nz, params->nx * params->ny * params->nz, L.np};
+    for (int s = 0; s < 2; ++s) {
+        lat->ph.a[s] = (float)(params->tau[s] - 0.5);
+        for (int a = 0; a < 3; ++a) lat->ph.g[s][a] = (float)params->g[s][a];
+    }
+    lat->ph.G = (float)params->G;
+    lat->cl = collide_launch_shape(lat->g);
+    lat->stream = (hipStream_t)stream;
+    lat->ws = (char*)d_workspace;
+    lat->t = 0;
+    lat->nbound = 0;
+    lat->geometry = false;
+    lat->initialized = false;
+    *out = lat;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, const float* d_xi) {
+    if (!lat || !d_solid || !d_xi) return fail(MCLBM_EINVAL, "NULL argument");
+    const Geo& g = lat->g;
+    launch_neighbour_bits(d_solid, lat->nbm(), g, lat->stream);
+    int* counts = (int*)(lat->ws + lat->L.counts);
+    int* bad = (int*)(lat->ws + lat->L.bad);
+    launch_boundary_list(lat->nbm(), d_xi, counts, lat->misc_int(), lat->list(), lat->xil(), bad, g,
+                         lat->stream);
+    HIP_TRY(hipGetLastError());
+    const int nb = boundary_blocks(g);
+    std::vector<int> hbad(nb);
+    int total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, lat->misc_int(), sizeof(int), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipMemcpyAsync(hbad.data(), bad, nb * sizeof(int), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    for (int b = 0; b < nb; ++b)
+        if (hbad[b]) {
+            lat->geometry = false;
+            return fail(MCLBM_EINVAL, "|xi| must be < 1 at solid voxels with a fluid neighbour");
+        }
+    lat->nbound = total;
+    lat->geometry = true;
+    lat->initialized = false;
+    lat->t = 0;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_boundary_count(const mclbm_lattice* lat, int64_t* count) {
+    if (!lat || !count) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->geometry) return fail(MCLBM_ESTATE, "geometry not set");
+    *count = lat->nbound;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_init_equilibrium(mclbm_lattice* lat, const float* d_rho) {
+    if (!lat || !d_rho) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->geometry) return fail(MCLBM_ESTATE, "set_geometry must come first");
+    // state at t = 0; the codecs' reference density of the previous level is R[1]
+    lat->with_codec([&](auto c) {
+        using C = decltype(c);
+        launch_init<C>(lat->pops<C>(), lat->nbm(), d_rho, lat->R(1), lat->g, lat->stream);
+    });
+    HIP_TRY(hipGetLastError());
+    lat->t = 0;
+    lat->initialized = true;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
+    if (!lat) return fail(MCLBM_EINVAL, "NULL handle");
+    if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    for (int32_t k = 0; k < nsteps; ++k) {
+        const int odd = (int)(lat->t & 1);
+        float2* psi = lat->R((int)(lat->t & 1));
+        const float2* rprev = lat->R((int)((lat->t + 1) & 1));
+        auto mark = [&](int k) -> hipError_t {
+            if (!lat->profiling) return hipSuccess;
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            lat->ev[k].push_back(e);
+            return hipEventRecord(e, lat->stream);
+        };
+        lat->with_codec([&](auto c) {
+            using C = decltype(c);
+            mark(0);
+            launch_density<C>(lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, odd, lat->stream);
+            mark(0);
+            mark(1);
+            launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, lat->g, lat->stream);
+            mark(1);
+            mark(2);
+            launch_collide_stream<C>(lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, lat->ph, odd, lat->cl,
+                                     lat->stream);
+            mark(2);
+        });
+        lat->t += 1;
+    }
+    HIP_TRY(hipGetLastError());
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_get_time(const mclbm_lattice* lat, int64_t* t) {
+    if (!lat || !t) return fail(MCLBM_EINVAL, "NULL argument");
+    *t = lat->t;
+    return MCLBM_OK;
+}
+
+static mclbm_status readout(mclbm_lattice* lat, float* r, float* u, float* F, float* P) {
+    if (!lat || !(r || u || F || P)) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    lat->fields(r, u, F, P, nullptr, nullptr);
+    HIP_TRY(hipGetLastError());
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_read_density(mclbm_lattice* lat, float* d_rho) {
+    return readout(lat, d_rho, nullptr, nullptr, nullptr);
+}
+mclbm_status mclbm_read_velocity(mclbm_lattice* lat, float* d_u) {
+    return readout(lat, nullptr, d_u, nullptr, nullptr);
+}
+mclbm_status mclbm_read_force(mclbm_lattice* lat, float* d_F) {
+    return readout(lat, nullptr, nullptr, d_F, nullptr);
+}
+mclbm_status mclbm_read_pressure(mclbm_lattice* lat, float* d_P) {
+    return readout(lat, nullptr, nullptr, nullptr, d_P);
+}
+
+mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]) {
+    if (!lat || !h_out) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    lat->fields(nullptr, nullptr, nullptr, nullptr, lat->partial(), lat->diag_out());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h_out, lat->diag_out(), 7 * sizeof(double), hipMemcpyDeviceToHost,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    if (h_out[5] > 0) return fail(MCLBM_ENONFINITE, "non-finite density or velocity");
+    return MCLBM_OK;
+}
+
+// Saved state: [header 256 B][moving planes][rest planes][previous-level densities]
+struct StateHeader {
+    uint64_t magic;
+    int64_t t;
+    int32_t nx, ny, nz, storage;
+};
+static constexpr uint64_t kMagic = 0x4d434c424d535431ull;  // "MCLBMST1"
+
+mclbm_status mclbm_state_bytes(const mclbm_lattice* lat, size_t* bytes) {
+    if (!lat || !bytes) return fail(MCLBM_EINVAL, "NULL argument");
+    *bytes = kAlign + align_up(lat->L.mv_bytes, kAlign) + align_up(lat->L.rest_bytes, kAlign) +
+             align_up(lat->L.r_bytes, kAlign);
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_save_state(mclbm_lattice* lat, void* d_dst) {
+    if (!lat || !d_dst) return fail(MCLBM_EINVAL, "NULL argument");
+    if (((uintptr_t)d_dst) % kAlign) return fail(MCLBM_EINVAL, "state buffer must be 256-byte aligned");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    const Layout& L = lat->L;
+    char* dst = (char*)d_dst;
+    StateHeader h{kMagic, lat->t, lat->p.nx, lat->p.ny, lat->p.nz, lat->p.storage};
+    uint64_t words[4];
+    static_assert(sizeof(h) == sizeof(words), "header is four 64-bit words");
+    std::memcpy(words, &h, sizeof(h));
+    launch_store_words((uint64_t*)dst, words, lat->stream);
+    size_t off = kAlign;
+    HIP_TRY(hipMemcpyAsync(dst + off, lat->ws + L.mv, L.mv_bytes, hipMemcpyDeviceToDevice, lat->stream));
+    off += align_up(L.mv_bytes, kAlign);
+    HIP_TRY(hipMemcpyAsync(dst + off, lat->ws + L.rest, L.rest_bytes, hipMemcpyDeviceToDevice, lat->stream));
+    off += align_up(L.rest_bytes, kAlign);
+    HIP_TRY(hipMemcpyAsync(dst + off, lat->R((int)((lat->t + 1) & 1)), L.r_bytes, hipMemcpyDeviceToDevice,
+                           lat->stream));
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src) {
+    if (!lat || !d_src) return fail(MCLBM_EINVAL, "NULL argument");
+    if (((uintptr_t)d_src) % kAlign) return fail(MCLBM_EINVAL, "state buffer must be 256-byte aligned");
+    if (!lat->geometry) return fail(MCLBM_ESTATE, "set_geometry must come first");
+    const Layout& L = lat->L;
+    const char* src = (const char*)d_src;
+    StateHeader h{};
+    HIP_TRY(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    if (h.magic != kMagic || h.nx != lat->p.nx || h.ny != lat->p.ny || h.nz != lat->p.nz ||
+        h.storage != lat->p.storage || h.t < 0)
+        return fail(MCLBM_EINVAL, "state buffer does not match this lattice");
+    size_t off = kAlign;
+    HIP_TRY(hipMemcpyAsync(lat->ws + L.mv, src + off, L.mv_bytes, hipMemcpyDeviceToDevice, lat->stream));
+    off += align_up(L.mv_bytes, kAlign);
+    HIP_TRY(hipMemcpyAsync(lat->ws + L.rest, src + off, L.rest_bytes, hipMemcpyDeviceToDevice, lat->stream));
+    off += align_up(L.rest_bytes, kAlign);
+    HIP_TRY(hipMemcpyAsync(lat->R((int)((h.t + 1) & 1)), src + off, L.r_bytes, hipMemcpyDeviceToDevice,
+                           lat->stream));
+    lat->t = h.t;
+    lat->initialized = true;
+    return MCLBM_OK;
+}
+
+static void drop_events(mclbm_lattice* lat) {
+    for (auto& v : lat->ev) {
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        v.clear();
+    }
+}
+
+mclbm_status mclbm_profile(mclbm_lattice* lat, int32_t enable) {
+    if (!lat) return fail(MCLBM_EINVAL, "NULL handle");
+    if (enable) drop_events(lat);
+    lat->profiling = enable != 0;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_profile_read(mclbm_lattice* lat, double h_ms[3], int64_t h_launches[3]) {
+    if (!lat || !h_ms || !h_launches) return fail(MCLBM_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        const size_t pairs = lat->ev[k].size() / 2;
+        for (size_t j = 0; j < pairs; ++j) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, lat->ev[k][2 * j], lat->ev[k][2 * j + 1]));
+            acc += ms;
+        }
+        h_ms[k] = acc;
+        h_launches[k] = (int64_t)pairs;
+    }
+    return MCLBM_OK;
+}
+
+void mclbm_destroy(mclbm_lattice* lat) {
+    if (!lat) return;
+    drop_events(lat);
+    delete lat;
+}
+
+const char* mclbm_status_string(mclbm_status s) {
+    switch (s) {
+        case MCLBM_OK: return "ok";
+        case MCLBM_EINVAL: return "invalid argument";
+        case MCLBM_EHIP: return "HIP runtime error";
+        case MCLBM_ENONFINITE: return "non-finite values in the state";
+        case MCLBM_ESTATE: return "call out of order";
+        case MCLBM_EVERSION: return "ABI version mismatch";
+    }
+    return "unknown status";
+}
+
+const char* mclbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

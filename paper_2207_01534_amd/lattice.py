@@ -1,0 +1,247 @@
+"""ctypes binding of ``libmclbm.so`` (C ABI in ``include/mclbm.h``).
+
+Argument marshalling only: every step of the lattice update runs in the HIP
+kernels of the library.  PyTorch supplies device memory (the workspace and
+the readout buffers) and the stream.  There is no CPU fallback: creating a
+:class:`Lattice` without the built library raises :class:`MclbmError`.
+"""
+import ctypes
+import enum
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmclbm.so")
+ABI_VERSION = 1
+
+_lib = None
+
+
+class MclbmError(RuntimeError):
+    pass
+
+
+class Storage(enum.IntEnum):
+    F32 = 0
+    F16 = 1
+    BF16 = 2
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tau", ctypes.c_double * 2),
+        ("G", ctypes.c_double),
+        ("g", (ctypes.c_double * 3) * 2),
+    ]
+
+
+_STATUS = {0: "MCLBM_OK", -1: "MCLBM_EINVAL", -2: "MCLBM_EHIP", -3: "MCLBM_ENONFINITE",
+           -4: "MCLBM_ESTATE", -5: "MCLBM_EVERSION"}
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _I32, _I64P, _SZP = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)
+_PP = ctypes.POINTER(_Params)
+SIGNATURES = [
+    ("mclbm_abi_version", ctypes.c_uint32, []),
+    ("mclbm_workspace_bytes", _I32, [_PP, _SZP]),
+    ("mclbm_create", _I32, [_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    ("mclbm_set_geometry", _I32, [_VP, _VP, _VP]),
+    ("mclbm_boundary_count", _I32, [_VP, _I64P]),
+    ("mclbm_init_equilibrium", _I32, [_VP, _VP]),
+    ("mclbm_step", _I32, [_VP, _I32]),
+    ("mclbm_get_time", _I32, [_VP, _I64P]),
+    ("mclbm_read_density", _I32, [_VP, _VP]),
+    ("mclbm_read_velocity", _I32, [_VP, _VP]),
+    ("mclbm_read_force", _I32, [_VP, _VP]),
+    ("mclbm_read_pressure", _I32, [_VP, _VP]),
+    ("mclbm_diagnostics", _I32, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    ("mclbm_state_bytes", _I32, [_VP, _SZP]),
+    ("mclbm_save_state", _I32, [_VP, _VP]),
+    ("mclbm_load_state", _I32, [_VP, _VP]),
+    ("mclbm_profile", _I32, [_VP, _I32]),
+    ("mclbm_profile_read", _I32, [_VP, ctypes.POINTER(ctypes.c_double), _I64P]),
+    ("mclbm_destroy", None, [_VP]),
+    ("mclbm_status_string", ctypes.c_char_p, [_I32]),
+    ("mclbm_last_error", ctypes.c_char_p, []),
+]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the built HIP library (raises MclbmError if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MclbmError(f"{path} not found: build it with `python -m paper_2207_01534_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if lib.mclbm_abi_version() != ABI_VERSION:
+        raise MclbmError("libmclbm ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != 0:
+        detail = _lib.mclbm_last_error().decode()
+        raise MclbmError(f"{what} failed: {_STATUS.get(status, status)}: {detail}")
+
+
+@dataclass
+class LatticeParams:
+    shape: tuple                               # (nx, ny, nz)
+    tau: tuple = (1.0, 1.0)
+    G: float = 3.5
+    g: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    storage: Storage = Storage.F32
+
+    def c(self):
+        p = _Params()
+        p.abi_version = ABI_VERSION
+        p.nx, p.ny, p.nz = (int(v) for v in self.shape)
+        p.storage = int(self.storage)
+        p.reserved = 0
+        p.tau[0], p.tau[1] = (float(v) for v in self.tau)
+        p.G = float(self.G)
+        for s in range(2):
+            for a in range(3):
+                p.g[s][a] = float(self.g[s][a])
+        return p
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def _dev_tensor(a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).contiguous()
+
+
+class Lattice:
+    """One two-component D3Q19 lattice living in a torch-owned device workspace."""
+
+    def __init__(self, params: LatticeParams, solid, xi=None, rho=None, device="cuda", stream=None):
+        lib = load_library()
+        self.params = params
+        self.device = torch.device(device)
+        nx, ny, nz = params.shape
+        self.dims = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self._cp = params.c()
+        nbytes = ctypes.c_size_t()
+        _check(lib.mclbm_workspace_bytes(ctypes.byref(self._cp), ctypes.byref(nbytes)), "workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.mclbm_create(ctypes.byref(self._cp), _ptr(self.workspace), nbytes.value,
+                                self.stream.cuda_stream, ctypes.byref(h)), "create")
+        self._h = h
+        self.set_geometry(solid, xi)
+        if rho is not None:
+            self.init_equilibrium(rho)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.mclbm_destroy(h)
+            self._h = None
+
+    # set-up ----------------------------------------------------------------
+    def set_geometry(self, solid, xi=None):
+        solid_t = _dev_tensor(solid, torch.uint8, self.device).reshape(self.dims)
+        if xi is None:
+            xi = torch.zeros(self.dims, dtype=torch.float32)
+        xi_t = _dev_tensor(xi, torch.float32, self.device).reshape(self.dims)
+        with torch.cuda.stream(self.stream):
+            _check(_lib.mclbm_set_geometry(self._h, _ptr(solid_t), _ptr(xi_t)), "set_geometry")
+
+    def boundary_count(self) -> int:
+        c = ctypes.c_int64()
+        _check(_lib.mclbm_boundary_count(self._h, ctypes.byref(c)), "boundary_count")
+        return c.value
+
+    def init_equilibrium(self, rho):
+        rho_t = _dev_tensor(rho, torch.float32, self.device).reshape((2,) + self.dims)
+        _check(_lib.mclbm_init_equilibrium(self._h, _ptr(rho_t)), "init_equilibrium")
+        self._keep = rho_t  # stream-ordered use; keep alive until the next sync point
+
+    # stepping --------------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(_lib.mclbm_step(self._h, int(n)), "step")
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        _check(_lib.mclbm_get_time(self._h, ctypes.byref(t)), "get_time")
+        return t.value
+
+    # readouts ----------------------------------------------------------------
+    def _out(self, shape):
+        return torch.empty(shape + self.dims, dtype=torch.float32, device=self.device)
+
+    def density(self) -> torch.Tensor:
+        o = self._out((2,))
+        _check(_lib.mclbm_read_density(self._h, _ptr(o)), "read_density")
+        return o
+
+    def velocity(self) -> torch.Tensor:
+        o = self._out((3,))
+        _check(_lib.mclbm_read_velocity(self._h, _ptr(o)), "read_velocity")
+        return o
+
+    def force(self) -> torch.Tensor:
+        o = self._out((2, 3))
+        _check(_lib.mclbm_read_force(self._h, _ptr(o)), "read_force")
+        return o
+
+    def pressure(self) -> torch.Tensor:
+        o = self._out(())
+        _check(_lib.mclbm_read_pressure(self._h, _ptr(o)), "read_pressure")
+        return o
+
+    def diagnostics(self, raise_nonfinite=True) -> dict:
+        out = (ctypes.c_double * 7)()
+        st = _lib.mclbm_diagnostics(self._h, out)
+        if st == -3 and not raise_nonfinite:
+            st = 0
+        _check(st, "diagnostics")
+        keys = ("mass1", "mass2", "S_w", "S_nw", "u_max", "nonfinite", "n_fluid")
+        return dict(zip(keys, list(out)))
+
+    # measurement -------------------------------------------------------------
+    KERNELS = ("density", "ivsd", "collide_stream")
+
+    def profile(self, enable: bool):
+        _check(_lib.mclbm_profile(self._h, 1 if enable else 0), "profile")
+
+    def profile_read(self) -> dict:
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_int64 * 3)()
+        _check(_lib.mclbm_profile_read(self._h, ms, cnt), "profile_read")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
+
+    # checkpoints -------------------------------------------------------------
+    def state_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.mclbm_state_bytes(self._h, ctypes.byref(b)), "state_bytes")
+        return b.value
+
+    def save(self, out: torch.Tensor = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        _check(_lib.mclbm_save_state(self._h, _ptr(out)), "save_state")
+        return out
+
+    def load(self, state: torch.Tensor):
+        _check(_lib.mclbm_load_state(self._h, _ptr(state)), "load_state")

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/mclbm.h, and validates parameters without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2207_01534_amd import lattice as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mclbm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mclbm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libmclbm.so is not built (python -m paper_2207_01534_amd.build)")
+    return L.load_library()
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    declared = _declared()
+    assert len(declared) >= 19
+    bound = {name for name, _, _ in L.SIGNATURES}
+    assert set(declared) == bound, set(declared) ^ bound
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_abi_version(lib):
+    assert lib.mclbm_abi_version() == L.ABI_VERSION
+    assert "#define MCLBM_ABI_VERSION %du" % L.ABI_VERSION in open(HEADER).read()
+
+
+def _bytes(lib, **kw):
+    p = L.LatticeParams(**kw).c()
+    n = ctypes.c_size_t()
+    st = lib.mclbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_accounts_for_storage(lib):
+    st32, b32 = _bytes(lib, shape=(64, 32, 16))
+    st16, b16 = _bytes(lib, shape=(64, 32, 16), storage=L.Storage.F16)
+    assert st32 == 0 and st16 == 0
+    n = 64 * 32 * 16
+    # 36 moving planes shrink from 4 to 2 bytes per node
+    assert b32 - b16 >= 36 * 2 * n
+    assert b32 >= 38 * 4 * n + 2 * 8 * n
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(shape=(2, 8, 8)), -1),
+    (dict(shape=(8, 8, 8), tau=(0.5, 1.0)), -1),
+    (dict(shape=(8, 8, 8), tau=(1.0, float("nan"))), -1),
+    (dict(shape=(2048, 1024, 1024)), -1),
+    (dict(shape=(8, 8, 8), G=float("inf")), -1),
+])
+def test_invalid_parameters_rejected(lib, kw, code):
+    st, _ = _bytes(lib, **kw)
+    assert st == code
+    assert lib.mclbm_last_error()
+
+
+def test_version_mismatch_rejected(lib):
+    p = L.LatticeParams(shape=(8, 8, 8)).c()
+    p.abi_version = 99
+    n = ctypes.c_size_t()
+    assert lib.mclbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -5
+
+
+def test_create_validates_workspace_without_touching_it(lib):
+    p = L.LatticeParams(shape=(8, 8, 8)).c()
+    n = ctypes.c_size_t()
+    assert lib.mclbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
+    h = ctypes.c_void_p()
+    # too small and misaligned workspaces are refused before any device access
+    assert lib.mclbm_create(ctypes.byref(p), 256, n.value - 1, None, ctypes.byref(h)) == -1
+    assert lib.mclbm_create(ctypes.byref(p), 257, n.value, None, ctypes.byref(h)) == -1
+    assert lib.mclbm_create(ctypes.byref(p), None, n.value, None, ctypes.byref(h)) == -1
+    # a well-formed call only records the pointers (no device work happens here)
+    assert lib.mclbm_create(ctypes.byref(p), 1 << 20, n.value, None, ctypes.byref(h)) == 0
+    # stepping before geometry and initial state is refused
+    assert lib.mclbm_step(h, 1) == -4
+    assert lib.mclbm_step(h, -1) == -1
+    lib.mclbm_destroy(h)
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.mclbm_status_string(code)
