@@ -63,9 +63,9 @@ typedef enum {
 /* Storage of the populations between steps.  Arithmetic is FP32 in all
  * three; FP64 is used only in the mass / saturation / loss reductions.
  *   MCLBM_F32   38 FP32 values per node.
- *   MCLBM_F16   the 36 moving populations stored in FP16 as offsets from the
- *               lattice weight of the density-normalised population,
- *               q_i = f_i / rho_src - w_i, where rho_src is the density of
+ *   MCLBM_F16   the 36 moving populations stored in FP16 as offsets from
+ *               their lattice-weight share, q_i = (f_i - w_i rho_src) /
+ *               (rho1_src + rho2_src), where rho_src are the densities of
  *               the node that wrote the value one step earlier; the two rest
  *               populations stay FP32 and absorb the rounding residual of the
  *               node's moving populations, so component mass is conserved to
@@ -75,7 +75,7 @@ typedef enum { MCLBM_F32 = 0, MCLBM_F16 = 1, MCLBM_BF16 = 2 } mclbm_storage;
 
 typedef struct {
     uint32_t abi_version; /* must equal MCLBM_ABI_VERSION                         */
-    int32_t nx, ny, nz;   /* lattice extents, each >= 3, nx*ny*nz < 2^31          */
+    int32_t nx, ny, nz;   /* lattice extents, each >= 3, nx*ny*nz < 2^30          */
     int32_t storage;      /* mclbm_storage                                        */
     int32_t reserved;     /* must be 0                                            */
     double tau[2];        /* relaxation times tau^(1), tau^(2) > 0.5 (Eqs. 6-7)   */

@@ -1,6 +1,7 @@
 // Device-side building blocks of the two-component D3Q19 step for gfx950:
-// the velocity set, the population storage codecs, and the single-buffer
-// (AA-pattern) addressing with halfway bounce-back.
+// the velocity set, the population storage codecs, the single-buffer
+// (AA-pattern) addressing with halfway bounce-back, and the per-node
+// physics (forces, forced SRT collision).
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -26,58 +27,101 @@ __host__ __device__ constexpr float weight(int i) {
 }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
-// Bit layout of the per-node neighbourhood word: bit 0 = the node itself is
-// solid, bit i (1..18) = the neighbour x + e_i is solid.
+// Per-node neighbourhood word: bit 0 = the node itself is solid, bit i
+// (1..18) = the neighbour x + e_i is solid.
 constexpr uint32_t SELF_SOLID = 1u;
 constexpr uint32_t NB_BITS = ((1u << Q) - 1u) & ~1u;
 
 struct Geo {
     int nx, ny, nz;
-    int n;        // nx * ny * nz (< 2^31)
-    int np;       // population plane stride in elements (>= n)
+    int n;   // nx * ny * nz (< 2^30, so byte offsets of a plane fit in 32 bits)
+    int np;  // population plane stride in elements (>= n)
 };
 
-__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// Loads and stores at a 32-bit element offset from a wave-uniform base, so
+// that the compiler can address with a scalar base plus a 32-bit vector
+// offset instead of a 64-bit address per lane.
+template <class T>
+__device__ __forceinline__ T ld(const T* base, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st(T* base, uint32_t i, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
+// Node index and periodic neighbour offsets of one node.
+struct Nb {
+    uint32_t idx;
+    int ox[3], oy[3], oz[3];  // offsets of the -1 / 0 / +1 neighbour along each axis
+    __device__ __forceinline__ Nb(int x, int y, int z, const Geo& g) {
+        const int nxy = g.nx * g.ny;
+        idx = (uint32_t)(x + g.nx * y + nxy * z);
+        ox[0] = x == 0 ? g.nx - 1 : -1;
+        ox[1] = 0;
+        ox[2] = x == g.nx - 1 ? 1 - g.nx : 1;
+        oy[0] = (y == 0 ? g.ny - 1 : -1) * g.nx;
+        oy[1] = 0;
+        oy[2] = (y == g.ny - 1 ? 1 - g.ny : 1) * g.nx;
+        oz[0] = (z == 0 ? g.nz - 1 : -1) * nxy;
+        oz[1] = 0;
+        oz[2] = (z == g.nz - 1 ? 1 - g.nz : 1) * nxy;
+    }
+    // index of x + s e_i (s = +1 or -1)
+    __device__ __forceinline__ uint32_t at(int i, int s) const {
+        return idx + (uint32_t)(ox[1 + s * DX[i]] + oy[1 + s * DY[i]] + oz[1 + s * DZ[i]]);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Storage codecs.  Moving populations (i = 1..18) are stored in type T; the
 // rest population of each component always stays FP32.
 //   F32:  stored value = f.
-//   F16 / BF16: stored value q = f / rho_w - w_i, where rho_w is the density
-//         (at the previous time level) of the node that wrote the value; the
-//         decoder multiplies back with the same FP32 rho_w.
+//   F16 / BF16: stored value q = (f - w_i rho_w) / rhot_w, the offset of the
+//         population from its lattice-weight share of the writer's component
+//         density, scaled by the writer's total density rhot_w = rho1 + rho2
+//         (both at the previous time level, read back by the decoder from the
+//         same FP32 field).  Scaling by the total density keeps q bounded
+//         where one component's density vanishes; the decoder evaluates
+//         f = q rhot_w + w_i rho_w with one explicit FMA so that encoder and
+//         decoder agree bit for bit.
 // ---------------------------------------------------------------------------
 struct CodecF32 {
     using T = float;
     static constexpr bool kRef = false;
-    __device__ static __forceinline__ float dec(T h, float, float) { return h; }
-    __device__ static __forceinline__ T enc(float f, float, float) { return f; }
+    __device__ static __forceinline__ float dec(T h, float, float, float) { return h; }
+    __device__ static __forceinline__ T enc(float f, float, float, float) { return f; }
 };
 
 struct CodecF16 {
     using T = __half;
     static constexpr bool kRef = true;
-    __device__ static __forceinline__ float dec(T h, float w, float rho_w) {
-        return (__half2float(h) + w) * rho_w;
+    __device__ static __forceinline__ float dec(T h, float w, float rho_w, float rhot_w) {
+        return fmaf(__half2float(h), rhot_w, w * rho_w);
     }
-    __device__ static __forceinline__ T enc(float f, float w, float inv_rho) {
-        return __float2half_rn(f * inv_rho - w);
+    __device__ static __forceinline__ T enc(float f, float w, float rho_w, float inv_rhot_w) {
+        return __float2half_rn((f - w * rho_w) * inv_rhot_w);
     }
 };
 
 struct CodecBF16 {
     using T = __hip_bfloat16;
     static constexpr bool kRef = true;
-    __device__ static __forceinline__ float dec(T h, float w, float rho_w) {
-        return (__bfloat162float(h) + w) * rho_w;
+    __device__ static __forceinline__ float dec(T h, float w, float rho_w, float rhot_w) {
+        return fmaf(__bfloat162float(h), rhot_w, w * rho_w);
     }
-    __device__ static __forceinline__ T enc(float f, float w, float inv_rho) {
-        return __float2bfloat16(f * inv_rho - w);
+    __device__ static __forceinline__ T enc(float f, float w, float rho_w, float inv_rhot_w) {
+        return __float2bfloat16((f - w * rho_w) * inv_rhot_w);
     }
 };
 
-// Population storage: 36 moving planes of T (component-major, direction
-// 1..18) followed, elsewhere in the workspace, by 2 FP32 rest planes.
+__device__ __forceinline__ float inv_total(float2 r) {
+    const float t = r.x + r.y;
+    return t > 0.0f ? 1.0f / t : 0.0f;
+}
+
+// Population storage: 36 moving planes of T (component-major, directions
+// 1..18) and 2 FP32 rest planes, each plane np elements long.
 template <class C>
 struct Pops {
     typename C::T* mv;
@@ -87,102 +131,45 @@ struct Pops {
     }
 };
 
-// Wrapped coordinates of a node and its 26 neighbours' linear indices are
-// assembled from three wrapped x, y and z coordinates.
-struct Nbr {
-    int xs[3], ys[3], zs[3];  // index 0: -1, 1: 0, 2: +1
-    int nx, nxy;
-    __device__ __forceinline__ Nbr(int x, int y, int z, const Geo& g) {
-        xs[0] = wrap1(x - 1, g.nx); xs[1] = x; xs[2] = wrap1(x + 1, g.nx);
-        ys[0] = wrap1(y - 1, g.ny); ys[1] = y; ys[2] = wrap1(y + 1, g.ny);
-        zs[0] = wrap1(z - 1, g.nz); zs[1] = z; zs[2] = wrap1(z + 1, g.nz);
-        nx = g.nx;
-        nxy = g.nx * g.ny;
-    }
-    // index of x + s * e_i  (s = +1 or -1)
-    __device__ __forceinline__ int at(int i, int s) const {
-        return xs[1 + s * DX[i]] + nx * ys[1 + s * DY[i]] + nxy * zs[1 + s * DZ[i]];
-    }
-    __device__ __forceinline__ int self() const { return xs[1] + nx * ys[1] + nxy * zs[1]; }
-};
-
 // ---------------------------------------------------------------------------
-// AA-pattern single-buffer addressing.  The state at an even time level keeps
-// f_i(x) in slot (i, x).  An even step reads slots (i, x) and writes the
-// post-collision f*_i(x) into slot (opp i, x); an odd step reads f_i(x) from
-// slot (opp i, x - e_i) -- or from slot (i, x) when x - e_i is solid
-// (bounce-back) -- and writes f*_i(x) into slot (i, x + e_i) -- or into slot
-// (opp i, x) when x + e_i is solid.  Each thread reads exactly the slots it
-// later writes, so the update is race-free in place.
-// The node that wrote the value read as f_i(x) is x - e_i if that node is
-// fluid and x itself otherwise, in both parities.
+// AA-pattern single-buffer streaming with halfway bounce-back through ghost
+// slots.  The state at an even time level keeps f_i(x) in slot (i, x); at an
+// odd level f_i(x) sits in slot (opp i, x - e_i).
+//   even step at fluid x: read slots (i, x); write f*_i(x) to (opp i, x), and
+//     also to the ghost slot (i, x + e_i) when x + e_i is solid;
+//   odd step at fluid x:  read slots (opp i, x - e_i) -- a solid x - e_i holds
+//     the ghost copy of f*_(opp i)(x), i.e. the bounced population; write
+//     f*_i(x) to (i, x + e_i), and also to (opp i, x) when x + e_i is solid
+//     (the bounced population the next even step reads at home).
+// Every slot a thread reads or writes belongs to it alone within a step (a
+// solid node's slot (i, s) is reached only from the fluid node s - e_i), so
+// the update is race-free in place, and no read needs a bounce-back branch.
+// The node whose density normalised the value read as f_i(x) is x - e_i if
+// that node is fluid and x itself otherwise, in both parities.
 // ---------------------------------------------------------------------------
-struct ReadSlot {
-    int dir;     // direction plane to read
-    int idx;     // node index of the slot
-    int writer;  // node whose density normalised the stored value
-};
-
-__device__ __forceinline__ ReadSlot read_slot(int i, bool odd, uint32_t nbm, const Nbr& nb) {
-    const int self = nb.self();
-    const bool src_solid = (nbm >> opp(i)) & 1u;
-    const int src = nb.at(i, -1);
-    ReadSlot r;
-    r.writer = src_solid ? self : src;
-    if (!odd) {
-        r.dir = i;
-        r.idx = self;
-    } else if (src_solid) {
-        r.dir = i;
-        r.idx = self;
-    } else {
-        r.dir = opp(i);
-        r.idx = src;
-    }
-    return r;
-}
-
-struct WriteSlot {
-    int dir;
-    int idx;
-};
-
-__device__ __forceinline__ WriteSlot write_slot(int i, bool odd, uint32_t nbm, const Nbr& nb) {
-    const int self = nb.self();
-    WriteSlot w;
-    if (!odd) {
-        w.dir = opp(i);
-        w.idx = self;
-    } else if ((nbm >> i) & 1u) {
-        w.dir = opp(i);
-        w.idx = self;
-    } else {
-        w.dir = i;
-        w.idx = nb.at(i, +1);
-    }
-    return w;
-}
 
 // Load and decode the 19 incoming populations of both components at a fluid
-// node.  rprev: densities of the previous time level (used by F16/BF16 only).
+// node.  rprev: densities of the previous time level (F16/BF16 codecs only).
 template <class C>
 __device__ __forceinline__ void load_node(float (&f)[2][Q], const Pops<C>& P, const float2* rprev,
-                                          bool odd, uint32_t nbm, const Nbr& nb, int np) {
-    const int self = nb.self();
-    f[0][0] = P.rest[self];
-    f[1][0] = P.rest[(size_t)np + self];
+                                          bool odd, uint32_t nbm, const Nb& nb, int np) {
+    f[0][0] = ld(P.rest, nb.idx);
+    f[1][0] = ld(P.rest + np, nb.idx);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const ReadSlot r = read_slot(i, odd, nbm, nb);
-        const typename C::T h0 = P.plane(0, r.dir, np)[r.idx];
-        const typename C::T h1 = P.plane(1, r.dir, np)[r.idx];
+        const int dir = odd ? opp(i) : i;
+        const uint32_t at = odd ? nb.at(i, -1) : nb.idx;
+        const typename C::T h0 = ld(P.plane(0, dir, np), at);
+        const typename C::T h1 = ld(P.plane(1, dir, np), at);
         if constexpr (C::kRef) {
-            const float2 rw = rprev[r.writer];
-            f[0][i] = C::dec(h0, weight(i), rw.x);
-            f[1][i] = C::dec(h1, weight(i), rw.y);
+            const bool src_solid = (nbm >> opp(i)) & 1u;
+            const float2 rw = ld(rprev, src_solid ? nb.idx : nb.at(i, -1));
+            const float rt = rw.x + rw.y;
+            f[0][i] = C::dec(h0, weight(i), rw.x, rt);
+            f[1][i] = C::dec(h1, weight(i), rw.y, rt);
         } else {
-            f[0][i] = C::dec(h0, weight(i), 1.0f);
-            f[1][i] = C::dec(h1, weight(i), 1.0f);
+            f[0][i] = C::dec(h0, weight(i), 0.0f, 0.0f);
+            f[1][i] = C::dec(h1, weight(i), 0.0f, 0.0f);
         }
     }
 }
@@ -205,30 +192,40 @@ __device__ __forceinline__ float sum19(const float (&f)[Q]) {
 // not summing exactly to 1, and the FP16/BF16 rounding of the moving
 // populations is absorbed by the FP32 rest population.
 // mass: incoming component densities; rho_ref: this node's density as the
-// decoder will read it next step (used by the F16/BF16 codecs only).
+// decoder will read it next step (F16/BF16 codecs only).
 template <class C>
 __device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C>& P, const float (&mass)[2],
-                                           float2 rho_ref, bool odd, uint32_t nbm, const Nbr& nb,
-                                           int np) {
-    const int self = nb.self();
+                                           float2 rho_ref, bool odd, uint32_t nbm, const Nb& nb, int np) {
     float sum0 = 0.0f, sum1 = 0.0f;
-    float inv0 = 1.0f, inv1 = 1.0f;
-    if constexpr (C::kRef) {
-        inv0 = rho_ref.x > 0.0f ? 1.0f / rho_ref.x : 0.0f;
-        inv1 = rho_ref.y > 0.0f ? 1.0f / rho_ref.y : 0.0f;
-    }
+    const float inv_t = C::kRef ? inv_total(rho_ref) : 0.0f;
+    const float rt = rho_ref.x + rho_ref.y;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const WriteSlot w = write_slot(i, odd, nbm, nb);
-        const typename C::T h0 = C::enc(fs[0][i], weight(i), inv0);
-        const typename C::T h1 = C::enc(fs[1][i], weight(i), inv1);
-        P.plane(0, w.dir, np)[w.idx] = h0;
-        P.plane(1, w.dir, np)[w.idx] = h1;
-        sum0 += C::dec(h0, weight(i), rho_ref.x);
-        sum1 += C::dec(h1, weight(i), rho_ref.y);
+        const typename C::T h0 = C::enc(fs[0][i], weight(i), rho_ref.x, inv_t);
+        const typename C::T h1 = C::enc(fs[1][i], weight(i), rho_ref.y, inv_t);
+        const bool nb_solid = (nbm >> i) & 1u;
+        if (!odd) {
+            st(P.plane(0, opp(i), np), nb.idx, h0);
+            st(P.plane(1, opp(i), np), nb.idx, h1);
+            if (nb_solid) {  // ghost copy for the odd step's reads
+                const uint32_t s = nb.at(i, +1);
+                st(P.plane(0, i, np), s, h0);
+                st(P.plane(1, i, np), s, h1);
+            }
+        } else {
+            const uint32_t d = nb.at(i, +1);
+            st(P.plane(0, i, np), d, h0);
+            st(P.plane(1, i, np), d, h1);
+            if (nb_solid) {  // bounced population, read at home by the next even step
+                st(P.plane(0, opp(i), np), nb.idx, h0);
+                st(P.plane(1, opp(i), np), nb.idx, h1);
+            }
+        }
+        sum0 += C::dec(h0, weight(i), rho_ref.x, rt);
+        sum1 += C::dec(h1, weight(i), rho_ref.y, rt);
     }
-    P.rest[self] = mass[0] - sum0;
-    P.rest[(size_t)np + self] = mass[1] - sum1;
+    st(P.rest, nb.idx, mass[0] - sum0);
+    st(P.rest + np, nb.idx, mass[1] - sum1);
 }
 
 // Physical parameters in FP32.
@@ -240,17 +237,20 @@ struct Phys {
 
 // Forced SRT collision at one node (Eqs. 1, 2, 6-9), in place on the moving
 // populations f[s][1..18]; the rest population follows from mass balance in
-// store_node.  F: total force per component (Eq. 10).  Returns u through uo.
+// store_node.  F: total force per component (Eq. 10).  Returns u in uo.
+// Opposite directions (2k-1, 2k) share e.u and e.F up to sign, so the
+// equilibrium and source are split into their even and odd parts per pair.
 __device__ __forceinline__ void collide(float (&f)[2][Q], const float (&rho)[2], const float (&F)[2][3],
                                         const Phys& ph, float (&uo)[3]) {
     float j[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            if (DX[i]) j[0] += DX[i] * f[s][i];
-            if (DY[i]) j[1] += DY[i] * f[s][i];
-            if (DZ[i]) j[2] += DZ[i] * f[s][i];
+        for (int i = 1; i < Q; i += 2) {
+            const float d = f[s][i] - f[s][i + 1];
+            if (DX[i]) j[0] += DX[i] * d;
+            if (DY[i]) j[1] += DY[i] * d;
+            if (DZ[i]) j[2] += DZ[i] * d;
         }
     const float rt = rho[0] + rho[1];
     const float inv_rt = 1.0f / rt;
@@ -263,35 +263,45 @@ __device__ __forceinline__ void collide(float (&f)[2][Q], const float (&rho)[2],
     const float tau_s = (rho[0] * ph.a[0] + rho[1] * ph.a[1]) * inv_rt + 0.5f;
     const float om = 1.0f / tau_s;
     const float cf = 1.0f - 0.5f * om;
+    const float keep = 1.0f - om;
     const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const float uF = ux * F[s][0] + uy * F[s][1] + uz * F[s][2];
         const float r = rho[s];
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
+        for (int i = 1; i < Q; i += 2) {
+            const float w = weight(i);
             const float eu = DX[i] * ux + DY[i] * uy + DZ[i] * uz;
             const float eF = DX[i] * F[s][0] + DY[i] * F[s][1] + DZ[i] * F[s][2];
-            const float feq = weight(i) * r * (1.0f + 3.0f * eu + 4.5f * eu * eu - usq15);
-            const float S = weight(i) * (3.0f * (eF - uF) + 9.0f * eu * eF);
-            f[s][i] = f[s][i] - om * (f[s][i] - feq) + cf * S;
+            // f^eq = w r (1 + 3 eu + 4.5 eu^2 - 1.5 u^2),  S = w (3 (eF - uF) + 9 eu eF)
+            const float eq_even = w * r * (1.0f + 4.5f * eu * eu - usq15);
+            const float eq_odd = w * r * 3.0f * eu;
+            const float s_even = w * (9.0f * eu * eF - 3.0f * uF);
+            const float s_odd = w * 3.0f * eF;
+            const float g_even = om * eq_even + cf * s_even;
+            const float g_odd = om * eq_odd + cf * s_odd;
+            f[s][i] = keep * f[s][i] + (g_even + g_odd);
+            f[s][i + 1] = keep * f[s][i + 1] + (g_even - g_odd);
         }
     }
 }
 
 // Pseudopotential force sum sum_{i>=1} w_i psi(x + e_i) e_i for both
-// components, with psi supplied by a functor psi_at(i) -> float2.
+// components, with psi supplied by a functor psi_at(i) -> float2; opposite
+// pairs enter as differences.
 template <class PsiAt>
 __device__ __forceinline__ void psi_sum(PsiAt psi_at, float (&acc)[2][3]) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) acc[s][0] = acc[s][1] = acc[s][2] = 0.0f;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const float2 p = psi_at(i);
+    for (int i = 1; i < Q; i += 2) {
+        const float2 p = psi_at(i), q = psi_at(i + 1);
         const float w = weight(i);
-        if (DX[i]) { acc[0][0] += (w * DX[i]) * p.x; acc[1][0] += (w * DX[i]) * p.y; }
-        if (DY[i]) { acc[0][1] += (w * DY[i]) * p.x; acc[1][1] += (w * DY[i]) * p.y; }
-        if (DZ[i]) { acc[0][2] += (w * DZ[i]) * p.x; acc[1][2] += (w * DZ[i]) * p.y; }
+        const float d0 = w * (p.x - q.x), d1 = w * (p.y - q.y);
+        if (DX[i]) { acc[0][0] += DX[i] * d0; acc[1][0] += DX[i] * d1; }
+        if (DY[i]) { acc[0][1] += DY[i] * d0; acc[1][1] += DY[i] * d1; }
+        if (DZ[i]) { acc[0][2] += DZ[i] * d0; acc[1][2] += DZ[i] * d1; }
     }
 }
 

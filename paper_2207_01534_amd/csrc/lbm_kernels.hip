@@ -25,12 +25,12 @@ __global__ void k_neighbour_bits(const uint8_t* __restrict__ solid, uint32_t* __
     const int y = blockIdx.y;
     const int z = blockIdx.z;
     if (x >= g.nx) return;
-    const Nbr nb(x, y, z, g);
-    uint32_t m = solid[nb.self()] ? SELF_SOLID : 0u;
+    const Nb nb(x, y, z, g);
+    uint32_t m = solid[nb.idx] ? SELF_SOLID : 0u;
 #pragma unroll
     for (int i = 1; i < Q; ++i)
         if (solid[nb.at(i, +1)]) m |= (1u << i);
-    nbm[nb.self()] = m;
+    nbm[nb.idx] = m;
 }
 
 // A boundary solid node: solid with at least one fluid neighbour.
@@ -108,8 +108,8 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const float*
     const int y = blockIdx.y;
     const int z = blockIdx.z;
     if (x >= g.nx) return;
-    const Nbr nb(x, y, z, g);
-    const int self = nb.self();
+    const Nb nb(x, y, z, g);
+    const uint32_t self = nb.idx;
     const uint32_t m = nbm[self];
     if (m & SELF_SOLID) {
         rprev[self] = make_float2(0.f, 0.f);
@@ -123,51 +123,75 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const float*
         const float f0 = weight(i) * r0, f1 = weight(i) * r1;
         typename C::T h0, h1;
         if constexpr (C::kRef) {
-            // normalise by the density of the node that will be recorded as
-            // the writer of slot (i, x): x - e_i if fluid, else x.
+            // reference densities of the node recorded as the writer of
+            // slot (i, x): x - e_i if fluid, else x
             const bool src_solid = (m >> opp(i)) & 1u;
-            const int w = src_solid ? self : nb.at(i, -1);
-            const float rw0 = src_solid ? r0 : rho_in[w];
-            const float rw1 = src_solid ? r1 : rho_in[(size_t)g.n + w];
-            h0 = C::enc(f0, weight(i), rw0 > 0.f ? 1.0f / rw0 : 0.f);
-            h1 = C::enc(f1, weight(i), rw1 > 0.f ? 1.0f / rw1 : 0.f);
-            sum0 += C::dec(h0, weight(i), rw0);
-            sum1 += C::dec(h1, weight(i), rw1);
+            const uint32_t w = src_solid ? self : nb.at(i, -1);
+            const float2 rw = src_solid ? make_float2(r0, r1) : make_float2(rho_in[w], rho_in[(size_t)g.n + w]);
+            const float inv_t = inv_total(rw);
+            const float rt = rw.x + rw.y;
+            h0 = C::enc(f0, weight(i), rw.x, inv_t);
+            h1 = C::enc(f1, weight(i), rw.y, inv_t);
+            sum0 += C::dec(h0, weight(i), rw.x, rt);
+            sum1 += C::dec(h1, weight(i), rw.y, rt);
         } else {
-            h0 = C::enc(f0, weight(i), 1.f);
-            h1 = C::enc(f1, weight(i), 1.f);
-            sum0 += C::dec(h0, weight(i), 1.f);
-            sum1 += C::dec(h1, weight(i), 1.f);
+            h0 = C::enc(f0, weight(i), 0.f, 0.f);
+            h1 = C::enc(f1, weight(i), 0.f, 0.f);
+            sum0 += C::dec(h0, weight(i), 0.f, 0.f);
+            sum1 += C::dec(h1, weight(i), 0.f, 0.f);
         }
-        P.plane(0, i, g.np)[self] = h0;
-        P.plane(1, i, g.np)[self] = h1;
+        st(P.plane(0, i, g.np), self, h0);
+        st(P.plane(1, i, g.np), self, h1);
     }
     // rest population from the node mass (see store_node)
-    P.rest[self] = r0 - sum0;
-    P.rest[(size_t)g.np + self] = r1 - sum1;
+    st(P.rest, self, r0 - sum0);
+    st(P.rest + g.np, self, r1 - sum1);
+}
+
+// ---------------------------------------------------------------------------
+// Tiles of 64 x 4 nodes in one z plane.  Blocks are numbered on a 1D grid and
+// mapped XCD-aware: the hardware deals consecutive block ids round-robin to
+// the 8 XCDs, so block b takes tile (b mod 8) * per + b / 8 and every XCD
+// works through a contiguous run of neighbouring tiles, whose shared halo
+// rows then hit in that XCD's L2.
+// ---------------------------------------------------------------------------
+constexpr int TX = 64, TY = 4;
+constexpr int HX = TX + 2, HY = TY + 2;
+
+struct TileGrid {
+    int ntx, nty, ntiles, grid;
+};
+
+__device__ __forceinline__ bool tile_of_block(const TileGrid& T, int& bx, int& by, int& bz) {
+    const int per = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= T.ntiles) return false;
+    bx = tile % T.ntx;
+    by = (tile / T.ntx) % T.nty;
+    bz = tile / (T.ntx * T.nty);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
 // K1: densities.  psi[x] = (rho1, rho2) at fluid nodes, (0, 0) at solid.
 // ---------------------------------------------------------------------------
-template <class C>
-__global__ __launch_bounds__(256) void k_density(Pops<C> P, const uint32_t* __restrict__ nbm,
-                                                 const float2* __restrict__ rprev,
-                                                 float2* __restrict__ psi, Geo g, int odd) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+template <class C, bool ODD>
+__global__ __launch_bounds__(TX * TY) void k_density(Pops<C> P, const uint32_t* __restrict__ nbm,
+                                                     const float2* __restrict__ rprev,
+                                                     float2* __restrict__ psi, Geo g, TileGrid T) {
+    int bx, by, z;
+    if (!tile_of_block(T, bx, by, z)) return;
+    const int x = bx * TX + threadIdx.x, y = by * TY + threadIdx.y;
     if (x >= g.nx || y >= g.ny) return;
-    const Nbr nb(x, y, z, g);
-    const int self = nb.self();
-    const uint32_t m = nbm[self];
+    const Nb nb(x, y, z, g);
+    const uint32_t m = ld(nbm, nb.idx);
     if (m & SELF_SOLID) {
-        psi[self] = make_float2(0.f, 0.f);
+        st(psi, nb.idx, make_float2(0.f, 0.f));
         return;
     }
     float f[2][Q];
-    load_node<C>(f, P, rprev, odd != 0, m, nb, g.np);
-    psi[self] = make_float2(sum19(f[0]), sum19(f[1]));
+    load_node<C>(f, P, rprev, ODD, m, nb, g.np);
+    st(psi, nb.idx, make_float2(sum19(f[0]), sum19(f[1])));
 }
 
 // ---------------------------------------------------------------------------
@@ -184,13 +208,13 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
     const int x = idx % g.nx;
     const int y = (idx / g.nx) % g.ny;
     const int z = idx / (g.nx * g.ny);
-    const Nbr nb(x, y, z, g);
+    const Nb nb(x, y, z, g);
     const uint32_t m = nbm[idx];
     float den = 0.f, n0 = 0.f, n1 = 0.f;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if (!((m >> i) & 1u)) {
-            const float2 r = psi[nb.at(i, +1)];
+            const float2 r = ld((const float2*)psi, nb.at(i, +1));
             den += weight(i);
             n0 += weight(i) * r.x;
             n1 += weight(i) * r.y;
@@ -202,106 +226,86 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
 }
 
 // ---------------------------------------------------------------------------
-// K2: fused force + collision + streaming.
-// Block = 64 x 4 nodes of one (x, y) tile, marching over a chunk of z planes.
-// psi-hat planes z-1, z, z+1 of the tile plus a one-node halo sit in a
-// three-plane LDS ring; each new plane is loaded once per block.
+// K2: fused force + collision + streaming, one 64 x 4 tile of one z plane per
+// block.  The psi-hat values of planes z-1, z, z+1 over the tile and a
+// one-node halo are staged in LDS once (one barrier); each fluid node then
+// reads its 18 neighbours from LDS.
 // ---------------------------------------------------------------------------
-constexpr int TX = 64, TY = 4;
-constexpr int HX = TX + 2, HY = TY + 2;
-
-__device__ __forceinline__ void load_psi_plane(float2 (*ring)[HX], const float2* __restrict__ psi,
-                                               int x0, int y0, int pz, const Geo& g) {
-    const int z = wrap1(pz, g.nz);
-    for (int k = threadIdx.y * TX + threadIdx.x; k < HX * HY; k += TX * TY) {
-        const int hy = k / HX, hx = k - hy * HX;
-        const int gx = wrap1(x0 + hx - 1, g.nx);
-        const int gy = wrap1(y0 + hy - 1, g.ny);
-        float2 v = make_float2(0.f, 0.f);
-        if (gx < g.nx && gy < g.ny) v = psi[gx + g.nx * (gy + g.ny * z)];
-        ring[hy][hx] = v;
-    }
-}
-
-template <class C>
+template <class C, bool ODD>
 __global__ __launch_bounds__(TX * TY) void k_collide_stream(
     Pops<C> P, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
-    const float2* __restrict__ psi, Geo g, Phys ph, int odd, int ntx, int nty, int tz, int ntiles) {
-    // XCD-aware tile order: hardware deals consecutive block ids round-robin
-    // to the 8 XCDs; give each XCD a contiguous run of tiles so that the
-    // halo planes its neighbouring tiles share stay in that XCD's L2.
-    const int per = gridDim.x >> 3;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= ntiles) return;
-    const int bx = tile % ntx;
-    const int by = (tile / ntx) % nty;
-    const int bz = tile / (ntx * nty);
+    const float2* __restrict__ psi, Geo g, Phys ph, TileGrid T) {
+    int bx, by, z;
+    if (!tile_of_block(T, bx, by, z)) return;
     const int x0 = bx * TX, y0 = by * TY;
-    const int z0 = bz * tz;
-    const int z1 = min(z0 + tz, g.nz);
 
-    __shared__ float2 ring[3][HY][HX];
-    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-    const bool in_tile = x < g.nx && y < g.ny;
-
-    load_psi_plane(ring[(z0 + 2) % 3], psi, x0, y0, z0 - 1, g);
-    load_psi_plane(ring[z0 % 3], psi, x0, y0, z0, g);
-    for (int z = z0; z < z1; ++z) {
-        load_psi_plane(ring[(z + 1) % 3], psi, x0, y0, z + 1, g);
-        __syncthreads();
-        if (in_tile) {
-            const Nbr nb(x, y, z, g);
-            const int self = nb.self();
-            const uint32_t m = nbm[self];
-            if (!(m & SELF_SOLID)) {
-                float f[2][Q];
-                load_node<C>(f, P, rprev, odd != 0, m, nb, g.np);
-                float rho[2] = {sum19(f[0]), sum19(f[1])};
-                float acc[2][3];
-                const int tx = threadIdx.x + 1, ty = threadIdx.y + 1;
-                psi_sum([&](int i) { return ring[(z + 3 + DZ[i]) % 3][ty + DY[i]][tx + DX[i]]; }, acc);
-                float F[2][3];
-                total_force(rho, acc, ph, F);
-                float u[3];
-                collide(f, rho, F, ph, u);
-                const float2 rself = ring[z % 3][ty][tx];
-                store_node<C>(f, P, rho, rself, odd != 0, m, nb, g.np);
-            }
+    __shared__ float2 tile[3][HY][HX];
+    {
+        const int nxy = g.nx * g.ny;
+        const int zs[3] = {(z == 0 ? g.nz - 1 : z - 1) * nxy, z * nxy, (z == g.nz - 1 ? 0 : z + 1) * nxy};
+        for (int k = threadIdx.y * TX + threadIdx.x; k < 3 * HX * HY; k += TX * TY) {
+            const int pl = k / (HX * HY);
+            const int r = k - pl * (HX * HY);
+            const int hy = r / HX, hx = r - hy * HX;
+            int gx = x0 + hx - 1, gy = y0 + hy - 1;
+            gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+            gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+            float2 v = make_float2(0.f, 0.f);
+            if (gx < g.nx && gy < g.ny) v = ld(psi, (uint32_t)(gx + g.nx * gy + zs[pl]));
+            tile[pl][hy][hx] = v;
         }
-        __syncthreads();
     }
+    __syncthreads();
+
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    const Nb nb(x, y, z, g);
+    const uint32_t m = ld(nbm, nb.idx);
+    if (m & SELF_SOLID) return;
+
+    float f[2][Q];
+    load_node<C>(f, P, rprev, ODD, m, nb, g.np);
+    const float rho[2] = {sum19(f[0]), sum19(f[1])};
+    const int tx = threadIdx.x + 1, ty = threadIdx.y + 1;
+    float acc[2][3];
+    psi_sum([&](int i) { return tile[1 + DZ[i]][ty + DY[i]][tx + DX[i]]; }, acc);
+    float F[2][3];
+    total_force(rho, acc, ph, F);
+    float u[3];
+    collide(f, rho, F, ph, u);
+    store_node<C>(f, P, rho, tile[1][ty][tx], ODD, m, nb, g.np);
 }
 
 // ---------------------------------------------------------------------------
 // Readouts and diagnostics at the current time level (psi already filled by
 // k_density + k_ivsd for this level).
 // ---------------------------------------------------------------------------
-template <class C>
-__global__ __launch_bounds__(256) void k_fields(Pops<C> P, const uint32_t* __restrict__ nbm,
-                                                const float2* __restrict__ rprev,
-                                                const float2* __restrict__ psi, Geo g, Phys ph, int odd,
-                                                float* __restrict__ o_rho, float* __restrict__ o_u,
-                                                float* __restrict__ o_F, float* __restrict__ o_P,
-                                                double* __restrict__ partial) {
+template <class C, bool ODD>
+__global__ __launch_bounds__(TX * TY) void k_fields(Pops<C> P, const uint32_t* __restrict__ nbm,
+                                                    const float2* __restrict__ rprev,
+                                                    const float2* __restrict__ psi, Geo g, Phys ph,
+                                                    float* __restrict__ o_rho, float* __restrict__ o_u,
+                                                    float* __restrict__ o_F, float* __restrict__ o_P,
+                                                    double* __restrict__ partial) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
     const bool inside = x < g.nx && y < g.ny;
     double d[7] = {0, 0, 0, 0, 0, 0, 0};  // m1, m2, water, snw, |u|max, bad, nfluid
     if (inside) {
-        const Nbr nb(x, y, z, g);
-        const int self = nb.self();
+        const Nb nb(x, y, z, g);
+        const uint32_t self = nb.idx;
         const size_t n = (size_t)g.n;
         const uint32_t m = nbm[self];
         float rho[2] = {0.f, 0.f}, u[3] = {0.f, 0.f, 0.f}, F[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
         float pr = 0.f;
         if (!(m & SELF_SOLID)) {
             float f[2][Q];
-            load_node<C>(f, P, rprev, odd != 0, m, nb, g.np);
+            load_node<C>(f, P, rprev, ODD, m, nb, g.np);
             rho[0] = sum19(f[0]);
             rho[1] = sum19(f[1]);
             float acc[2][3];
-            psi_sum([&](int i) { return psi[nb.at(i, +1)]; }, acc);
+            psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, acc);
             total_force(rho, acc, ph, F);
             collide(f, rho, F, ph, u);  // computes u; the collided f is discarded
             // Eq. (12), ordered pairs: P = c_s^2 (rho1 + rho2) + c_s^2 G rho1 rho2
@@ -385,7 +389,16 @@ void launch_store_words(uint64_t* dst, const uint64_t (&w)[4], hipStream_t s) {
 }
 
 static dim3 row_grid(const Geo& g) { return dim3((g.nx + 63) / 64, g.ny, g.nz); }
-static dim3 tile_grid(const Geo& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
+static dim3 tile_grid3(const Geo& g) { return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz); }
+
+static TileGrid tiles(const Geo& g) {
+    TileGrid T;
+    T.ntx = (g.nx + TX - 1) / TX;
+    T.nty = (g.ny + TY - 1) / TY;
+    T.ntiles = T.ntx * T.nty * g.nz;
+    T.grid = ((T.ntiles + 7) / 8) * 8;
+    return T;
+}
 
 void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hipStream_t s) {
     hipLaunchKernelGGL(k_neighbour_bits, row_grid(g), dim3(64), 0, s, solid, nbm, g);
@@ -411,7 +424,11 @@ void launch_init(const Pops<C>& P, const uint32_t* nbm, const float* rho, float2
 template <class C>
 void launch_density(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, float2* psi,
                     const Geo& g, int odd, hipStream_t s) {
-    hipLaunchKernelGGL(k_density<C>, tile_grid(g), dim3(64, 4), 0, s, P, nbm, rprev, psi, g, odd);
+    const TileGrid T = tiles(g);
+    if (odd)
+        hipLaunchKernelGGL((k_density<C, true>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, T);
+    else
+        hipLaunchKernelGGL((k_density<C, false>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, T);
 }
 
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
@@ -421,31 +438,20 @@ void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* n
                        g);
 }
 
-CollideLaunch collide_launch_shape(const Geo& g) {
-    CollideLaunch L;
-    L.ntx = (g.nx + TX - 1) / TX;
-    L.nty = (g.ny + TY - 1) / TY;
-    const int per_plane = L.ntx * L.nty;
-    const int target = 2048;  // blocks wanted in flight across the 256 CUs
-    int chunks = (target + per_plane - 1) / per_plane;
-    if (chunks < 1) chunks = 1;
-    if (chunks > g.nz) chunks = g.nz;
-    L.tz = (g.nz + chunks - 1) / chunks;
-    chunks = (g.nz + L.tz - 1) / L.tz;
-    L.ntiles = per_plane * chunks;
-    L.grid = ((L.ntiles + 7) / 8) * 8;
-    return L;
-}
-
 template <class C>
 void launch_collide_stream(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,
-                           const Geo& g, const Phys& ph, int odd, const CollideLaunch& L, hipStream_t s) {
-    hipLaunchKernelGGL(k_collide_stream<C>, dim3(L.grid), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, ph,
-                       odd, L.ntx, L.nty, L.tz, L.ntiles);
+                           const Geo& g, const Phys& ph, int odd, hipStream_t s) {
+    const TileGrid T = tiles(g);
+    if (odd)
+        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev,
+                           psi, g, ph, T);
+    else
+        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev,
+                           psi, g, ph, T);
 }
 
 int fields_blocks(const Geo& g) {
-    const dim3 gr = tile_grid(g);
+    const dim3 gr = tile_grid3(g);
     return (int)(gr.x * gr.y * gr.z);
 }
 
@@ -453,8 +459,12 @@ template <class C>
 void launch_fields(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,
                    const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F,
                    float* o_P, double* partial, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_fields<C>, tile_grid(g), dim3(64, 4), 0, s, P, nbm, rprev, psi, g, ph, odd, o_rho,
-                       o_u, o_F, o_P, partial);
+    if (odd)
+        hipLaunchKernelGGL((k_fields<C, true>), tile_grid3(g), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, ph,
+                           o_rho, o_u, o_F, o_P, partial);
+    else
+        hipLaunchKernelGGL((k_fields<C, false>), tile_grid3(g), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, ph,
+                           o_rho, o_u, o_F, o_P, partial);
     if (partial)
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, (const double*)partial,
                            fields_blocks(g), out);
@@ -466,8 +476,7 @@ void launch_fields(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, c
     template void launch_density<C>(const Pops<C>&, const uint32_t*, const float2*, float2*,           \
                                     const Geo&, int, hipStream_t);                                     \
     template void launch_collide_stream<C>(const Pops<C>&, const uint32_t*, const float2*,             \
-                                           const float2*, const Geo&, const Phys&, int,                \
-                                           const CollideLaunch&, hipStream_t);                         \
+                                           const float2*, const Geo&, const Phys&, int, hipStream_t);  \
     template void launch_fields<C>(const Pops<C>&, const uint32_t*, const float2*, const float2*,      \
                                    const Geo&, const Phys&, int, float*, float*, float*, float*,       \
                                    double*, double*, hipStream_t);

@@ -5,10 +5,6 @@
 
 namespace mclbm {
 
-struct CollideLaunch {
-    int ntx, nty, tz, ntiles, grid;
-};
-
 void launch_store_words(uint64_t* dst, const uint64_t (&w)[4], hipStream_t s);
 void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hipStream_t s);
 int boundary_blocks(const Geo& g);
@@ -23,10 +19,9 @@ void launch_density(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, 
                     const Geo& g, int odd, hipStream_t s);
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
                  const Geo& g, hipStream_t s);
-CollideLaunch collide_launch_shape(const Geo& g);
 template <class C>
 void launch_collide_stream(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,
-                           const Geo& g, const Phys& ph, int odd, const CollideLaunch& L, hipStream_t s);
+                           const Geo& g, const Phys& ph, int odd, hipStream_t s);
 int fields_blocks(const Geo& g);
 template <class C>
 void launch_fields(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,

@@ -77,7 +77,7 @@ mclbm_status check_params(const mclbm_params* p) {
     if (p->abi_version != MCLBM_ABI_VERSION) return fail(MCLBM_EVERSION, "abi_version mismatch");
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail(MCLBM_EINVAL, "extents must be >= 3");
     const double n = (double)p->nx * p->ny * p->nz;
-    if (n + 512 >= 2147483647.0) return fail(MCLBM_EINVAL, "nx*ny*nz must be < 2^31");
+    if (n + 512 >= 1073741824.0) return fail(MCLBM_EINVAL, "nx*ny*nz must be < 2^30");
     if (p->storage < MCLBM_F32 || p->storage > MCLBM_BF16) return fail(MCLBM_EINVAL, "bad storage");
     if (p->reserved != 0) return fail(MCLBM_EINVAL, "reserved must be 0");
     for (int s = 0; s < 2; ++s) {
@@ -96,7 +96,6 @@ struct mclbm_lattice {
     mclbm_params p;
     Geo g;
     Phys ph;
-    CollideLaunch cl;
     Layout L;
     hipStream_t stream;
     char* ws;
@@ -184,7 +183,6 @@ mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t 
         for (int a = 0; a < 3; ++a) lat->ph.g[s][a] = (float)params->g[s][a];
     }
     lat->ph.G = (float)params->G;
-    lat->cl = collide_launch_shape(lat->g);
     lat->stream = (hipStream_t)stream;
     lat->ws = (char*)d_workspace;
     lat->t = 0;
@@ -268,8 +266,7 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
             launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, lat->g, lat->stream);
             mark(1);
             mark(2);
-            launch_collide_stream<C>(lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, lat->ph, odd, lat->cl,
-                                     lat->stream);
+            launch_collide_stream<C>(lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, lat->ph, odd, lat->stream);
             mark(2);
         });
         lat->t += 1;
@@ -313,6 +310,11 @@ mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]) {
     HIP_TRY(hipMemcpyAsync(h_out, lat->diag_out(), 7 * sizeof(double), hipMemcpyDeviceToHost,
                            lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
+    // the kernels return counts and sums; saturations are fractions of the fluid voxels
+    if (h_out[6] > 0) {
+        h_out[2] /= h_out[6];
+        h_out[3] /= h_out[6];
+    }
     if (h_out[5] > 0) return fail(MCLBM_ENONFINITE, "non-finite density or velocity");
     return MCLBM_OK;
 }

@@ -134,14 +134,21 @@ def constant_xi(solid, value):
     return xi
 
 
-def inlet_drainage_rho(solid, buffer=3):
-    """Component 1 fills the inlet buffer x < buffer; component 2 fills the rest."""
+def inlet_drainage_rho(solid, buffer=3, width=5.0):
+    """Component 1 fills the fluid reservoir formed by the inlet buffer (x < buffer)
+    and, across the periodic x boundary, the outlet buffer (x >= nx - buffer);
+    component 2 fills the rest.  The two interfaces carry the diffuse tanh
+    profile of the paper's initialisation (Sec. 3.1, Eq. 16) in one dimension,
+    with width W = 5, centred on the buffer edges."""
     nz, ny, nx = solid.shape
-    rho1 = np.full((nz, ny, nx), RHO_MINOR)
-    rho2 = np.full((nz, ny, nx), RHO_MAJOR)
-    rho1[:, :, :buffer] = RHO_MAJOR
-    rho2[:, :, :buffer] = RHO_MINOR
-    rho = np.stack([rho1, rho2])
+    x = np.arange(nx, dtype=np.float64)
+    centre = -0.5                              # between x = nx - 1 and x = 0
+    d = np.abs((x - centre + nx / 2.0) % nx - nx / 2.0)   # periodic distance to the centre
+    half = float(buffer)                       # reservoir spans both buffers
+    t = np.tanh(2.0 * (d - half) / width)
+    r1 = 0.5 * (RHO_MAJOR + RHO_MINOR) - 0.5 * (RHO_MAJOR - RHO_MINOR) * t
+    r2 = (RHO_MAJOR + RHO_MINOR) - r1
+    rho = np.stack([np.broadcast_to(r1, (nz, ny, nx)), np.broadcast_to(r2, (nz, ny, nx))]).copy()
     rho[:, solid != 0] = 0.0
     return rho
 

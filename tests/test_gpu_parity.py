@@ -47,6 +47,10 @@ def test_droplet32_200_steps_literal_config():
     do = orc.diagnostics()
     assert d["mass1"] == pytest.approx(do[0], rel=1e-6)
     assert d["mass2"] == pytest.approx(do[1], rel=1e-6)
+    assert d["S_w"] == pytest.approx(do[2], abs=1.0 / w.n_fluid)   # one node may flip at a tie
+    assert d["S_nw"] == pytest.approx(do[3], rel=1e-5)
+    assert d["u_max"] == pytest.approx(do[4], rel=1e-4)
+    assert d["nonfinite"] == 0 and d["n_fluid"] == w.n_fluid
 
 
 def test_droplet32_at_paper_cohesion():
