@@ -155,6 +155,43 @@ mclbm_status mclbm_state_bytes(const mclbm_lattice* lat, size_t* bytes);
 mclbm_status mclbm_save_state(mclbm_lattice* lat, void* d_dst);
 mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src);
 
+/* ---- Differentiation with respect to the adhesion parameter xi ---------
+ * Loss: the smooth non-wetting saturation over a region (the water
+ * saturation of Sec. 4.1 with the node count replaced by the component-1
+ * fraction), L = (1/|R|) sum over fluid voxels x in R of
+ * rho1(x) / (rho1(x) + rho2(x)), reduced in FP64.  d_region: uint8[N],
+ * nonzero = in R.  These entry points need MCLBM_F32 storage (EINVAL
+ * otherwise). */
+
+/* L at the current time level; synchronises the stream. */
+mclbm_status mclbm_loss_snw(mclbm_lattice* lat, const uint8_t* d_region, double* h_L);
+
+/* Bytes of the checkpoint buffer for nsteps steps saved every `every`
+ * steps: ceil(nsteps/every) population states. */
+mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes);
+
+/* Bytes of the work buffer mclbm_gradient_snw needs: `every` recomputed
+ * states and psi-hat fields plus the adjoint fields. */
+mclbm_status mclbm_adjoint_work_bytes(const mclbm_lattice* lat, int32_t every, size_t* bytes);
+
+/* mclbm_step(nsteps) that also copies the state into slot k of d_ckpt
+ * before step k*every (k = 0, 1, ...).  d_ckpt: device, 256-byte aligned,
+ * >= mclbm_checkpoint_bytes. */
+mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t every, void* d_ckpt,
+                                     size_t bytes);
+
+/* Reverse sweep: dL/dxi for the loss at the current time level, through the
+ * nsteps steps recorded by mclbm_step_checkpointed (same nsteps and every;
+ * the lattice must not have been stepped since).  Each segment of `every`
+ * steps is recomputed from its checkpoint into d_work, then the adjoint
+ * steps run backwards through it (adjoint of streaming with bounce-back,
+ * of the forced collision, Eqs. 1-2, 6-9, and of the forces and virtual
+ * solid densities, Eqs. 10-15).  d_grad_xi: double[N] (output; written in
+ * full, non-zero only at solid voxels with a fluid neighbour).  The
+ * lattice's state is left unchanged.  Asynchronous on the stream. */
+mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
+                                const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi);
+
 /* Per-kernel timing of mclbm_step with HIP events recorded on the lattice's
  * stream around each launch (measurement support; two event records per
  * launch while enabled, no device memory).

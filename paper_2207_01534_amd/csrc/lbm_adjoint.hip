@@ -1,0 +1,408 @@
+// Reverse mode of the two-component D3Q19 step with respect to the per-voxel
+// adhesion parameter xi (Eqs. 13-15), for FP32 population storage.
+//
+// One forward step maps f(t) -> f(t+1) through
+//   rho = sum_i f_i,  psi-hat = rho (fluid) | chi N / D (boundary solid),
+//   A^s = sum_i w_i e_i psi-hat^s(x+e_i),  F^s = -G rho^s A^(other s) + rho^s g^s,
+//   u, tau_s, f* = (1-om) f + om f^eq + (1 - om/2) S,  then streaming.
+// Its adjoint runs as three kernels per step, with lambda = dL/df(t+1):
+//   k_adj_collide  per fluid x: lambda*_i(x) = lambda_i(x+e_i) (or the
+//                  bounced lambda at home), the vector-Jacobian product of
+//                  the local collision, giving the local part of dL/df(t)
+//                  and the adjoint Abar of the pseudopotential sums;
+//   k_adj_ivsd     per boundary solid y: psibar(y) = -sum_k w_k e_k .
+//                  Abar(y+e_k), which yields dL/dxi(y) and the adjoint Nbar
+//                  of the virtual-density numerator;
+//   k_adj_rho      per fluid z: the non-local density adjoint
+//                  rhobar(z) = -sum_k w_k e_k . Abar(z+e_k)
+//                              + sum_{solid z+e_m} w_m Nbar(z+e_m).
+// dL/df_i(t) at a fluid node is lambda_loc_i + rhobar, kept as the two parts
+// and added where the next reverse step gathers them.
+#include "lbm_adjoint.hpp"
+
+namespace mclbm {
+
+using CF = CodecF32;
+
+// ---------------------------------------------------------------------------
+// Loss L = (1/|R|) sum_{fluid x in R} rho1 / (rho1 + rho2), FP64 partials.
+// ---------------------------------------------------------------------------
+template <bool ODD>
+__global__ __launch_bounds__(256) void k_loss_partial(Pops<CF> P, const uint32_t* __restrict__ nbm,
+                                                      const uint8_t* __restrict__ region, Geo g,
+                                                      double* __restrict__ partial) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    double v = 0.0, c = 0.0;
+    if (x < g.nx) {
+        const Nb nb(x, y, z, g);
+        const uint32_t m = nbm[nb.idx];
+        if (!(m & SELF_SOLID) && region[nb.idx]) {
+            float f[2][Q];
+            load_node<CF>(f, P, nullptr, ODD, m, nb, g.np);
+            const double r0 = sum19(f[0]), r1 = sum19(f[1]);
+            v = r0 / (r0 + r1);
+            c = 1.0;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        v += __shfl_xor(v, off);
+        c += __shfl_xor(c, off);
+    }
+    __shared__ double red[4][2];
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = v;
+        red[threadIdx.x >> 6][1] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
+        const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        partial[(size_t)b * 2 + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_loss_final(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
+    __shared__ double red[2][1024];
+    const int t = threadIdx.x;
+    double v = 0.0, c = 0.0;
+    for (int b = t; b < nblocks; b += 1024) {
+        v += partial[(size_t)b * 2];
+        c += partial[(size_t)b * 2 + 1];
+    }
+    red[0][t] = v;
+    red[1][t] = c;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (t < off) {
+            red[0][t] += red[0][t + off];
+            red[1][t] += red[1][t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = red[1][0] > 0 ? red[0][0] / red[1][0] : 0.0;
+        out[1] = red[1][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Seed at the final time: dL/df_i = dL/drho, identical over i; it is stored
+// as lambda_loc = 0 plus rhobar = (rho2, -rho1) / (rho1+rho2)^2 / |R|.
+// ---------------------------------------------------------------------------
+template <bool ODD>
+__global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const uint32_t* __restrict__ nbm,
+                                                  const uint8_t* __restrict__ region, Geo g,
+                                                  const double* __restrict__ loss, float* __restrict__ lam,
+                                                  float2* __restrict__ rbar) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx) return;
+    const Nb nb(x, y, z, g);
+    const size_t n = (size_t)g.n;
+    for (int k = 0; k < 2 * Q; ++k) lam[k * n + nb.idx] = 0.0f;
+    const uint32_t m = nbm[nb.idx];
+    float2 r = make_float2(0.f, 0.f);
+    if (!(m & SELF_SOLID) && region[nb.idx] && loss[1] > 0) {
+        float f[2][Q];
+        load_node<CF>(f, P, nullptr, ODD, m, nb, g.np);
+        const double r0 = sum19(f[0]), r1 = sum19(f[1]);
+        const double rt = r0 + r1;
+        const double s = 1.0 / (rt * rt * loss[1]);
+        r = make_float2((float)(r1 * s), (float)(-r0 * s));
+    }
+    rbar[nb.idx] = r;
+}
+
+// ---------------------------------------------------------------------------
+// A1: adjoint of streaming and of the local collision at fluid nodes.
+// ---------------------------------------------------------------------------
+template <bool ODD>
+__global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const uint32_t* __restrict__ nbm,
+                                                     const float2* __restrict__ psi,
+                                                     const float* __restrict__ lam_next,
+                                                     const float2* __restrict__ rbar_next,
+                                                     float* __restrict__ lam_cur, float* __restrict__ abar,
+                                                     Geo g, Phys ph) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx) return;
+    const Nb nb(x, y, z, g);
+    const size_t n = (size_t)g.n;
+    const uint32_t m = nbm[nb.idx];
+    if (m & SELF_SOLID) {
+        for (int k = 0; k < 6; ++k) abar[k * n + nb.idx] = 0.0f;
+        return;
+    }
+    // forward quantities of this node at time t
+    float f[2][Q];
+    load_node<CF>(f, P, nullptr, ODD, m, nb, g.np);
+    const float rho[2] = {sum19(f[0]), sum19(f[1])};
+    float A[2][3];
+    psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, A);
+    float F[2][3];
+    total_force(rho, A, ph, F);
+    float j[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            j[0] += DX[i] * f[s][i];
+            j[1] += DY[i] * f[s][i];
+            j[2] += DZ[i] * f[s][i];
+        }
+    const float rt = rho[0] + rho[1];
+    const float inv_rt = 1.0f / rt;
+    const float u[3] = {(j[0] + 0.5f * (F[0][0] + F[1][0])) * inv_rt, (j[1] + 0.5f * (F[0][1] + F[1][1])) * inv_rt,
+                        (j[2] + 0.5f * (F[0][2] + F[1][2])) * inv_rt};
+    const float tau_s = (rho[0] * ph.a[0] + rho[1] * ph.a[1]) * inv_rt + 0.5f;
+    const float om = 1.0f / tau_s;
+    const float cf = 1.0f - 0.5f * om;
+    const float usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+
+    // lambda* = dL/df*: the adjoint of streaming gathers from downstream
+    float ls[2][Q];
+    {
+        const float2 rb0 = rbar_next[nb.idx];
+        ls[0][0] = lam_next[nb.idx] + rb0.x;
+        ls[1][0] = lam_next[(size_t)Q * n + nb.idx] + rb0.y;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const bool wall = (m >> i) & 1u;
+            const uint32_t at = wall ? nb.idx : nb.at(i, +1);
+            const int dir = wall ? opp(i) : i;
+            const float2 rb = rbar_next[at];
+            ls[0][i] = lam_next[(size_t)dir * n + at] + rb.x;
+            ls[1][i] = lam_next[(size_t)(Q + dir) * n + at] + rb.y;
+        }
+    }
+
+    // vector-Jacobian product of f* = (1-om) f + om f^eq(rho, u) + (1 - om/2) S(u, F)
+    float om_bar = 0.f;
+    float rb[2] = {0.f, 0.f};
+    float M0[2] = {0.f, 0.f};
+    float V[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float Wv[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const float uF = u[0] * F[s][0] + u[1] * F[s][1] + u[2] * F[s][2];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float w = weight(i);
+            const float eu = DX[i] * u[0] + DY[i] * u[1] + DZ[i] * u[2];
+            const float eF = DX[i] * F[s][0] + DY[i] * F[s][1] + DZ[i] * F[s][2];
+            const float B = 1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * usq;
+            const float feq = w * rho[s] * B;
+            const float S = w * (3.0f * (eF - uF) + 9.0f * eu * eF);
+            const float l = ls[s][i];
+            om_bar += l * (feq - f[s][i] - 0.5f * S);
+            const float lw = l * w;
+            rb[s] += om * lw * B;
+            M0[s] += lw;
+            const float c1 = lw * (3.0f + 9.0f * eu);
+            const float c2 = lw * eF;
+            if (DX[i]) { V[s][0] += c1 * DX[i]; Wv[s][0] += c2 * DX[i]; }
+            if (DY[i]) { V[s][1] += c1 * DY[i]; Wv[s][1] += c2 * DY[i]; }
+            if (DZ[i]) { V[s][2] += c1 * DZ[i]; Wv[s][2] += c2 * DZ[i]; }
+        }
+    }
+    float ubar[3], Fbar[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ubar[a] = 0.f;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float t0 = V[s][a] - 3.0f * u[a] * M0[s];
+            ubar[a] += om * rho[s] * t0 + cf * (9.0f * Wv[s][a] - 3.0f * F[s][a] * M0[s]);
+            Fbar[s][a] = cf * t0;
+        }
+    }
+    // om = 1/tau_s, tau_s = (rho1 a1 + rho2 a2)/rho + 1/2
+    const float tau_bar = -om * om * om_bar;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) rb[s] += tau_bar * (ph.a[s] - (tau_s - 0.5f)) * inv_rt;
+    // u = (j + (F1 + F2)/2) / rho
+    const float Pbar[3] = {ubar[0] * inv_rt, ubar[1] * inv_rt, ubar[2] * inv_rt};
+    const float uu = (ubar[0] * u[0] + ubar[1] * u[1] + ubar[2] * u[2]) * inv_rt;
+    rb[0] -= uu;
+    rb[1] -= uu;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Fbar[s][a] += 0.5f * Pbar[a];
+    // F^s = -G rho^s A^(other) + rho^s g^s
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int o = 1 - s;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) rb[s] += Fbar[s][a] * (-ph.G * A[o][a] + ph.g[s][a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        abar[(size_t)a * n + nb.idx] = -ph.G * rho[1] * Fbar[1][a];        // adjoint of A^(1)
+        abar[(size_t)(3 + a) * n + nb.idx] = -ph.G * rho[0] * Fbar[0][a];  // adjoint of A^(2)
+    }
+    // local part of dL/df_i(t): direct term, momentum term, density term
+    const float keep = 1.0f - om;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float ej = DX[i] * Pbar[0] + DY[i] * Pbar[1] + DZ[i] * Pbar[2];
+            lam_cur[(size_t)(s * Q + i) * n + nb.idx] = keep * ls[s][i] + ej + rb[s];
+        }
+}
+
+// psibar(y) = -sum_k w_k e_k . Abar(y + e_k), both components.
+__device__ __forceinline__ float2 psi_adjoint(const float* __restrict__ abar, const Nb& nb, size_t n) {
+    float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+        const uint32_t at = nb.at(k, +1);
+        const float w = weight(k);
+        float d0 = 0.f, d1 = 0.f;
+        if (DX[k]) { d0 += DX[k] * abar[at]; d1 += DX[k] * abar[3 * n + at]; }
+        if (DY[k]) { d0 += DY[k] * abar[n + at]; d1 += DY[k] * abar[4 * n + at]; }
+        if (DZ[k]) { d0 += DZ[k] * abar[2 * n + at]; d1 += DZ[k] * abar[5 * n + at]; }
+        p0 -= w * d0;
+        p1 -= w * d1;
+    }
+    return make_float2(p0, p1);
+}
+
+// ---------------------------------------------------------------------------
+// A2: boundary solid nodes.  rho~^s = chi^s N^s / D with chi = 1 +- xi gives
+// dL/dxi = psibar^1 N^1/D - psibar^2 N^2/D and Nbar^s = psibar^s chi^s / D.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_ivsd(const int* __restrict__ list, const float* __restrict__ xil,
+                                                  int count, const uint32_t* __restrict__ nbm,
+                                                  const float2* __restrict__ psi, const float* __restrict__ abar,
+                                                  Geo g, double* __restrict__ grad_acc,
+                                                  float2* __restrict__ nbar) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int idx = list[k];
+    const int x = idx % g.nx;
+    const int y = (idx / g.nx) % g.ny;
+    const int z = idx / (g.nx * g.ny);
+    const Nb nb(x, y, z, g);
+    const uint32_t m = nbm[idx];
+    const float2 pb = psi_adjoint(abar, nb, (size_t)g.n);
+    float den = 0.f, n0 = 0.f, n1 = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if (!((m >> i) & 1u)) {
+            const float2 r = psi[nb.at(i, +1)];
+            den += weight(i);
+            n0 += weight(i) * r.x;
+            n1 += weight(i) * r.y;
+        }
+    const float inv = 1.0f / den;
+    const float v = xil[k];
+    grad_acc[k] += (double)(pb.x * n0 * inv) - (double)(pb.y * n1 * inv);
+    nbar[idx] = make_float2(pb.x * (1.0f + v) * inv, pb.y * (1.0f - v) * inv);
+}
+
+// ---------------------------------------------------------------------------
+// A3: non-local density adjoint at fluid nodes.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_rho(const uint32_t* __restrict__ nbm, const float* __restrict__ abar,
+                                                 const float2* __restrict__ nbar, Geo g,
+                                                 float2* __restrict__ rbar) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx) return;
+    const Nb nb(x, y, z, g);
+    const uint32_t m = nbm[nb.idx];
+    if (m & SELF_SOLID) return;
+    float2 r = psi_adjoint(abar, nb, (size_t)g.n);
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if ((m >> i) & 1u) {
+            const float2 nv = nbar[nb.at(i, +1)];
+            r.x += weight(i) * nv.x;
+            r.y += weight(i) * nv.y;
+        }
+    rbar[nb.idx] = r;
+}
+
+__global__ void k_zero_words(uint32_t* __restrict__ p, size_t nwords) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_grad_scatter(const int* __restrict__ list, int count, const double* __restrict__ acc,
+                               double* __restrict__ grad) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) grad[list[k]] = acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static dim3 rows(const Geo& g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
+
+int loss_blocks(const Geo& g) {
+    const dim3 r = rows(g);
+    return (int)(r.x * r.y * r.z);
+}
+
+void launch_loss(const Pops<CF>& P, const uint32_t* nbm, const uint8_t* region, const Geo& g, int odd,
+                 double* partial, double* out, hipStream_t s) {
+    if (odd)
+        hipLaunchKernelGGL(k_loss_partial<true>, rows(g), dim3(256), 0, s, P, nbm, region, g, partial);
+    else
+        hipLaunchKernelGGL(k_loss_partial<false>, rows(g), dim3(256), 0, s, P, nbm, region, g, partial);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, s, (const double*)partial, loss_blocks(g), out);
+}
+
+void launch_adj_seed(const Pops<CF>& P, const uint32_t* nbm, const uint8_t* region, const Geo& g, int odd,
+                     const double* loss, float* lam, float2* rbar, hipStream_t s) {
+    if (odd)
+        hipLaunchKernelGGL(k_adj_seed<true>, rows(g), dim3(256), 0, s, P, nbm, region, g, loss, lam, rbar);
+    else
+        hipLaunchKernelGGL(k_adj_seed<false>, rows(g), dim3(256), 0, s, P, nbm, region, g, loss, lam, rbar);
+}
+
+void launch_adj_collide(const Pops<CF>& P, const uint32_t* nbm, const float2* psi, const float* lam_next,
+                        const float2* rbar_next, float* lam_cur, float* abar, const Geo& g, const Phys& ph,
+                        int odd, hipStream_t s) {
+    if (odd)
+        hipLaunchKernelGGL(k_adj_collide<true>, rows(g), dim3(256), 0, s, P, nbm, psi, lam_next, rbar_next,
+                           lam_cur, abar, g, ph);
+    else
+        hipLaunchKernelGGL(k_adj_collide<false>, rows(g), dim3(256), 0, s, P, nbm, psi, lam_next, rbar_next,
+                           lam_cur, abar, g, ph);
+}
+
+void launch_adj_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, const float2* psi,
+                     const float* abar, const Geo& g, double* grad_acc, float2* nbar, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_adj_ivsd, dim3((count + 255) / 256), dim3(256), 0, s, list, xil, count, nbm, psi, abar,
+                       g, grad_acc, nbar);
+}
+
+void launch_adj_rho(const uint32_t* nbm, const float* abar, const float2* nbar, const Geo& g, float2* rbar,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_rho, rows(g), dim3(256), 0, s, nbm, abar, nbar, g, rbar);
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const size_t words = bytes / 4;
+    if (!words) return;
+    const size_t blocks = (words + 255) / 256;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s,
+                       (uint32_t*)p, words);
+}
+
+void launch_grad_scatter(const int* list, int count, const double* acc, double* grad, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_grad_scatter, dim3((count + 255) / 256), dim3(256), 0, s, list, count, acc, grad);
+}
+
+}  // namespace mclbm

@@ -229,11 +229,14 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
 // K2: fused force + collision + streaming, one 64 x 4 tile of one z plane per
 // block.  The psi-hat values of planes z-1, z, z+1 over the tile and a
 // one-node halo are staged in LDS once (one barrier); each fluid node then
-// reads its 18 neighbours from LDS.
+// reads its 18 neighbours from LDS.  P is the state read, D the state
+// written: the same buffer for the in-place step, two buffers when a step is
+// recomputed into a separate slot (the AA addressing writes every slot the
+// next step reads, so an out-of-place step produces a complete state).
 // ---------------------------------------------------------------------------
 template <class C, bool ODD>
 __global__ __launch_bounds__(TX * TY) void k_collide_stream(
-    Pops<C> P, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
+    Pops<C> P, Pops<C> D, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
     const float2* __restrict__ psi, Geo g, Phys ph, TileGrid T) {
     int bx, by, z;
     if (!tile_of_block(T, bx, by, z)) return;
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(TX * TY) void k_collide_stream(
     total_force(rho, acc, ph, F);
     float u[3];
     collide(f, rho, F, ph, u);
-    store_node<C>(f, P, rho, tile[1][ty][tx], ODD, m, nb, g.np);
+    store_node<C>(f, D, rho, tile[1][ty][tx], ODD, m, nb, g.np);
 }
 
 // ---------------------------------------------------------------------------
@@ -439,14 +442,14 @@ void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* n
 }
 
 template <class C>
-void launch_collide_stream(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,
-                           const Geo& g, const Phys& ph, int odd, hipStream_t s) {
+void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const uint32_t* nbm, const float2* rprev,
+                           const float2* psi, const Geo& g, const Phys& ph, int odd, hipStream_t s) {
     const TileGrid T = tiles(g);
     if (odd)
-        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev,
+        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(T.grid), dim3(TX, TY), 0, s, P, D, nbm, rprev,
                            psi, g, ph, T);
     else
-        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev,
+        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(T.grid), dim3(TX, TY), 0, s, P, D, nbm, rprev,
                            psi, g, ph, T);
 }
 
@@ -475,8 +478,9 @@ void launch_fields(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, c
                                  hipStream_t);                                                         \
     template void launch_density<C>(const Pops<C>&, const uint32_t*, const float2*, float2*,           \
                                     const Geo&, int, hipStream_t);                                     \
-    template void launch_collide_stream<C>(const Pops<C>&, const uint32_t*, const float2*,             \
-                                           const float2*, const Geo&, const Phys&, int, hipStream_t);  \
+    template void launch_collide_stream<C>(const Pops<C>&, const Pops<C>&, const uint32_t*,            \
+                                           const float2*, const float2*, const Geo&, const Phys&, int, \
+                                           hipStream_t);                                               \
     template void launch_fields<C>(const Pops<C>&, const uint32_t*, const float2*, const float2*,      \
                                    const Geo&, const Phys&, int, float*, float*, float*, float*,       \
                                    double*, double*, hipStream_t);

@@ -20,8 +20,8 @@ void launch_density(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, 
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
                  const Geo& g, hipStream_t s);
 template <class C>
-void launch_collide_stream(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,
-                           const Geo& g, const Phys& ph, int odd, hipStream_t s);
+void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const uint32_t* nbm, const float2* rprev,
+                           const float2* psi, const Geo& g, const Phys& ph, int odd, hipStream_t s);
 int fields_blocks(const Geo& g);
 template <class C>
 void launch_fields(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,

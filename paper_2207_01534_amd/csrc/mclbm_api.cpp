@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/mclbm.h"
+#include "lbm_adjoint.hpp"
 #include "lbm_kernels.hpp"
 
 using namespace mclbm;
@@ -266,7 +267,8 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
             launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, lat->g, lat->stream);
             mark(1);
             mark(2);
-            launch_collide_stream<C>(lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, lat->ph, odd, lat->stream);
+            launch_collide_stream<C>(lat->pops<C>(), lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, lat->ph, odd,
+                                     lat->stream);
             mark(2);
         });
         lat->t += 1;
@@ -376,6 +378,161 @@ mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src) {
                            lat->stream));
     lat->t = h.t;
     lat->initialized = true;
+    return MCLBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Loss and adjoint (FP32 population storage)
+// ---------------------------------------------------------------------------
+static size_t state_slot_bytes(const Layout& L) {
+    return align_up(L.mv_bytes, kAlign) + align_up(L.rest_bytes, kAlign);
+}
+static Pops<CodecF32> slot_pops(char* base, const Layout& L) {
+    return Pops<CodecF32>{(float*)base, (float*)(base + align_up(L.mv_bytes, kAlign))};
+}
+
+mclbm_status mclbm_loss_snw(mclbm_lattice* lat, const uint8_t* d_region, double* h_L) {
+    if (!lat || !d_region || !h_L) return fail(MCLBM_EINVAL, "NULL argument");
+    if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    double out[2];
+    launch_loss(lat->pops<CodecF32>(), lat->nbm(), d_region, lat->g, (int)(lat->t & 1), lat->partial(),
+                lat->diag_out(), lat->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, lat->diag_out(), sizeof(out), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    *h_L = out[0];
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes) {
+    if (!lat || !bytes || nsteps < 1 || every < 1) return fail(MCLBM_EINVAL, "bad argument");
+    *bytes = (size_t)((nsteps + every - 1) / every) * state_slot_bytes(lat->L);
+    return MCLBM_OK;
+}
+
+struct AdjointWork {
+    char* seg;      // every state slots
+    char* psi;      // every psi-hat fields (n float2 each)
+    float* lam[2];  // [2][19][n]
+    float* abar;    // [6][n]
+    float2* rbar[2];
+    float2* nbar;
+    double* gacc;   // per boundary-list entry
+    size_t total;
+};
+
+static AdjointWork adjoint_layout(const mclbm_lattice* lat, int32_t every, char* base) {
+    const size_t n = (size_t)lat->g.n;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t at = off;
+        off = align_up(off + b, kAlign);
+        return base + at;
+    };
+    AdjointWork w;
+    w.seg = take((size_t)every * state_slot_bytes(lat->L));
+    w.psi = take((size_t)every * align_up(n * sizeof(float2), kAlign));
+    w.lam[0] = (float*)take(2 * Q * n * sizeof(float));
+    w.lam[1] = (float*)take(2 * Q * n * sizeof(float));
+    w.abar = (float*)take(6 * n * sizeof(float));
+    w.rbar[0] = (float2*)take(n * sizeof(float2));
+    w.rbar[1] = (float2*)take(n * sizeof(float2));
+    w.nbar = (float2*)take(n * sizeof(float2));
+    w.gacc = (double*)take(n * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+mclbm_status mclbm_adjoint_work_bytes(const mclbm_lattice* lat, int32_t every, size_t* bytes) {
+    if (!lat || !bytes || every < 1) return fail(MCLBM_EINVAL, "bad argument");
+    *bytes = adjoint_layout(lat, every, nullptr).total;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t every, void* d_ckpt,
+                                     size_t bytes) {
+    if (!lat || !d_ckpt || nsteps < 1 || every < 1) return fail(MCLBM_EINVAL, "bad argument");
+    if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
+    if (((uintptr_t)d_ckpt) % kAlign) return fail(MCLBM_EINVAL, "checkpoint buffer must be 256-byte aligned");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    size_t need = 0;
+    mclbm_checkpoint_bytes(lat, nsteps, every, &need);
+    if (bytes < need) return fail(MCLBM_EINVAL, "checkpoint buffer too small");
+    const Layout& L = lat->L;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        if (k % every == 0) {
+            char* slot = (char*)d_ckpt + (size_t)(k / every) * state_slot_bytes(L);
+            const Pops<CodecF32> d = slot_pops(slot, L);
+            HIP_TRY(hipMemcpyAsync(d.mv, lat->ws + L.mv, L.mv_bytes, hipMemcpyDeviceToDevice, lat->stream));
+            HIP_TRY(hipMemcpyAsync(d.rest, lat->ws + L.rest, L.rest_bytes, hipMemcpyDeviceToDevice, lat->stream));
+        }
+        mclbm_status st = mclbm_step(lat, 1);
+        if (st != MCLBM_OK) return st;
+    }
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
+                                const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
+    if (!lat || !d_ckpt || !d_region || !d_work || !d_grad_xi || nsteps < 1 || every < 1)
+        return fail(MCLBM_EINVAL, "bad argument");
+    if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
+    if (((uintptr_t)d_work) % kAlign || ((uintptr_t)d_ckpt) % kAlign)
+        return fail(MCLBM_EINVAL, "work and checkpoint buffers must be 256-byte aligned");
+    if (!lat->initialized || lat->t < nsteps) return fail(MCLBM_ESTATE, "state is not nsteps past the checkpoints");
+    const AdjointWork W = adjoint_layout(lat, every, (char*)d_work);
+    if (work_bytes < W.total) return fail(MCLBM_EINVAL, "work buffer too small");
+    const Layout& L = lat->L;
+    const Geo& g = lat->g;
+    const size_t n = (size_t)g.n;
+    const size_t slot = state_slot_bytes(L);
+    const size_t psi_stride = align_up(n * sizeof(float2), kAlign);
+    hipStream_t s = lat->stream;
+    const int64_t t_end = lat->t, t0 = t_end - nsteps;
+    const int nseg = (nsteps + every - 1) / every;
+
+    launch_zero(W.gacc, (size_t)lat->nbound * sizeof(double), s);
+    launch_zero(d_grad_xi, n * sizeof(double), s);
+    // seed from the final state (the lattice's current populations)
+    launch_loss(lat->pops<CodecF32>(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->partial(), lat->diag_out(),
+                s);
+    int cur = 0;  // lam[cur], rbar[cur] hold dL/df at the time level being processed
+    launch_adj_seed(lat->pops<CodecF32>(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->diag_out(), W.lam[cur],
+                    W.rbar[cur], s);
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t ta = t0 + (int64_t)seg * every;
+        const int len = (int)((ta + every <= t_end ? ta + every : t_end) - ta);
+        const Pops<CodecF32> c = slot_pops((char*)d_ckpt + (size_t)seg * slot, L);
+        const Pops<CodecF32> s0 = slot_pops(W.seg, L);
+        HIP_TRY(hipMemcpyAsync(s0.mv, c.mv, L.mv_bytes, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(s0.rest, c.rest, L.rest_bytes, hipMemcpyDeviceToDevice, s));
+        // recompute the segment's states and their psi-hat fields
+        for (int k = 0; k < len; ++k) {
+            const int odd = (int)((ta + k) & 1);
+            const Pops<CodecF32> sk = slot_pops(W.seg + (size_t)k * slot, L);
+            float2* psi = (float2*)(W.psi + (size_t)k * psi_stride);
+            launch_density<CodecF32>(sk, lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g, odd, s);
+            launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, g, s);
+            if (k + 1 < len) {
+                const Pops<CodecF32> sn = slot_pops(W.seg + (size_t)(k + 1) * slot, L);
+                launch_collide_stream<CodecF32>(sk, sn, lat->nbm(), psi, psi, g, lat->ph, odd, s);
+            }
+        }
+        // reverse steps
+        for (int k = len - 1; k >= 0; --k) {
+            const int odd = (int)((ta + k) & 1);
+            const Pops<CodecF32> sk = slot_pops(W.seg + (size_t)k * slot, L);
+            const float2* psi = (const float2*)(W.psi + (size_t)k * psi_stride);
+            const int nxt = cur, now = 1 - cur;
+            launch_adj_collide(sk, lat->nbm(), psi, W.lam[nxt], W.rbar[nxt], W.lam[now], W.abar, g, lat->ph, odd, s);
+            launch_adj_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, W.abar, g, W.gacc, W.nbar, s);
+            launch_adj_rho(lat->nbm(), W.abar, W.nbar, g, W.rbar[now], s);
+            cur = now;
+        }
+    }
+    launch_grad_scatter(lat->list(), lat->nbound, W.gacc, d_grad_xi, s);
+    HIP_TRY(hipGetLastError());
     return MCLBM_OK;
 }
 

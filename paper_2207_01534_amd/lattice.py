@@ -64,6 +64,11 @@ SIGNATURES = [
     ("mclbm_state_bytes", _I32, [_VP, _SZP]),
     ("mclbm_save_state", _I32, [_VP, _VP]),
     ("mclbm_load_state", _I32, [_VP, _VP]),
+    ("mclbm_loss_snw", _I32, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
+    ("mclbm_checkpoint_bytes", _I32, [_VP, _I32, _I32, _SZP]),
+    ("mclbm_adjoint_work_bytes", _I32, [_VP, _I32, _SZP]),
+    ("mclbm_step_checkpointed", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t]),
+    ("mclbm_gradient_snw", _I32, [_VP, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     ("mclbm_profile", _I32, [_VP, _I32]),
     ("mclbm_profile_read", _I32, [_VP, ctypes.POINTER(ctypes.c_double), _I64P]),
     ("mclbm_destroy", None, [_VP]),
@@ -147,7 +152,8 @@ class Lattice:
         _check(lib.mclbm_create(ctypes.byref(self._cp), _ptr(self.workspace), nbytes.value,
                                 self.stream.cuda_stream, ctypes.byref(h)), "create")
         self._h = h
-        self.set_geometry(solid, xi)
+        self.solid = _dev_tensor(solid, torch.uint8, self.device).reshape(self.dims)
+        self.set_geometry(self.solid, xi)
         if rho is not None:
             self.init_equilibrium(rho)
 
@@ -218,6 +224,39 @@ class Lattice:
         _check(st, "diagnostics")
         keys = ("mass1", "mass2", "S_w", "S_nw", "u_max", "nonfinite", "n_fluid")
         return dict(zip(keys, list(out)))
+
+    # loss and adjoint (FP32 storage) ----------------------------------------
+    def _region(self, region):
+        return _dev_tensor(region, torch.uint8, self.device).reshape(self.dims)
+
+    def loss_snw(self, region) -> float:
+        """Smooth non-wetting saturation over a region at the current time level."""
+        reg = self._region(region)
+        L = ctypes.c_double()
+        _check(_lib.mclbm_loss_snw(self._h, _ptr(reg), ctypes.byref(L)), "loss_snw")
+        return L.value
+
+    def step_checkpointed(self, nsteps: int, every: int) -> torch.Tensor:
+        """Advance nsteps, keeping a checkpoint every `every` steps; returns the buffer."""
+        b = ctypes.c_size_t()
+        _check(_lib.mclbm_checkpoint_bytes(self._h, int(nsteps), int(every), ctypes.byref(b)), "checkpoint_bytes")
+        ck = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        _check(_lib.mclbm_step_checkpointed(self._h, int(nsteps), int(every), _ptr(ck), b.value),
+               "step_checkpointed")
+        return ck
+
+    def gradient_snw(self, nsteps: int, every: int, checkpoints: torch.Tensor, region) -> torch.Tensor:
+        """dL/dxi (float64, shape (nz, ny, nx)) of the loss at the current time level
+        through the nsteps recorded by step_checkpointed."""
+        reg = self._region(region)
+        b = ctypes.c_size_t()
+        _check(_lib.mclbm_adjoint_work_bytes(self._h, int(every), ctypes.byref(b)), "adjoint_work_bytes")
+        work = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        grad = torch.empty(self.dims, dtype=torch.float64, device=self.device)
+        _check(_lib.mclbm_gradient_snw(self._h, int(nsteps), int(every), _ptr(checkpoints), _ptr(reg),
+                                       _ptr(work), b.value, _ptr(grad)), "gradient_snw")
+        self._keep = (reg, work)
+        return grad
 
     # measurement -------------------------------------------------------------
     KERNELS = ("density", "ivsd", "collide_stream")

@@ -1,0 +1,114 @@
+"""Hand-written adjoint (HIP, FP32) against central finite differences of the
+FP64 oracle, for the smooth non-wetting saturation loss with respect to the
+per-voxel adhesion parameter xi.  Bar: |g_adj - g_fd| <= 1e-3 max |g_fd|."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, OracleParams, lattice_tables
+from paper_2207_01534_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint64_fd.json")
+
+
+def _boundary_solid(solid):
+    e, _, _ = lattice_tables()
+    fluid = solid == 0
+    touch = np.zeros_like(fluid)
+    for i in range(1, 19):
+        touch |= np.roll(fluid, shift=(-e[i][2], -e[i][1], -e[i][0]), axis=(0, 1, 2))
+    return (solid != 0) & touch
+
+
+def _oracle_loss(shape, solid, xi64, rho, tau, G, g, steps, region):
+    o = Oracle(OracleParams(shape, tau=tau, G=G, g=g), solid, xi64)
+    o.init_equilibrium(rho.astype(np.float32).astype(np.float64))
+    o.run(steps)
+    return o.loss_snw(region)
+
+
+def _gpu_gradient(shape, solid, xi, rho, tau, G, g, steps, every, region):
+    import torch
+    from paper_2207_01534_amd.autograd import WettabilityLoss
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams
+    lat = Lattice(LatticeParams(shape=shape, tau=tau, G=G, g=g), torch.as_tensor(solid),
+                  torch.as_tensor(xi), None)
+    xi_t = torch.tensor(xi, device="cuda", requires_grad=True)
+    rho_t = torch.as_tensor(rho.astype(np.float32), device="cuda")
+    reg_t = torch.as_tensor(region, device="cuda")
+    L = WettabilityLoss.apply(xi_t, lat, rho_t, reg_t, steps, every)
+    L.backward()
+    torch.cuda.synchronize()
+    return float(L.detach()), xi_t.grad.double().cpu().numpy(), lat
+
+
+@pytest.mark.parametrize("steps,every", [(1, 1), (2, 1), (9, 4), (30, 7)])
+def test_small_gradient_against_oracle_fd(steps, every):
+    shape = (12, 10, 8)
+    nx, ny, nz = shape
+    print(f"[case] adjoint small {shape} steps={steps} every={every}", flush=True)
+    solid = wl.random_mask(shape, 0.25, seed=77)
+    xi = wl.uniform_xi(solid, -0.4, 0.4, seed=78)
+    rho = wl.tanh_droplet(shape, 3.0)
+    rho[:, solid != 0] = 0
+    tau, G, g = (1.5, 0.6), 3.5, ((2e-4, 0.0, 0.0), (0.0, 0.0, 0.0))
+    region = np.ones((nz, ny, nx), np.uint8)
+    L_gpu, grad, lat = _gpu_gradient(shape, solid, xi, rho, tau, G, g, steps, every, region)
+    xi64 = xi.astype(np.float64)
+    L_orc = _oracle_loss(shape, solid, xi64, rho, tau, G, g, steps, region)
+    assert L_gpu == pytest.approx(L_orc, rel=1e-5, abs=1e-7)
+    bs = _boundary_solid(solid)
+    assert lat.boundary_count() == int(bs.sum())
+    assert np.all(grad[~bs] == 0.0)                       # structural zeros
+    rng = np.random.default_rng(steps)
+    cand = np.argwhere(bs)
+    pick = cand[rng.choice(len(cand), size=10, replace=False)]
+    eps = 1e-3
+    fd = []
+    for z, y, x in pick:
+        xp, xm = xi64.copy(), xi64.copy()
+        xp[z, y, x] += eps
+        xm[z, y, x] -= eps
+        fd.append((_oracle_loss(shape, solid, xp, rho, tau, G, g, steps, region)
+                   - _oracle_loss(shape, solid, xm, rho, tau, G, g, steps, region)) / (2 * eps))
+    fd = np.array(fd)
+    adj = np.array([grad[z, y, x] for z, y, x in pick])
+    scale = np.abs(fd).max()
+    err = np.abs(adj - fd).max() / scale
+    print(f"[adjoint] steps={steps} max|fd|={scale:.3e} rel err={err:.3e}", flush=True)
+    assert scale > 0
+    assert err <= 1e-3
+    # directional derivative along a random direction over all boundary voxels
+    v = np.where(bs, rng.standard_normal(bs.shape), 0.0)
+    v /= np.abs(v).max()
+    dd = (_oracle_loss(shape, solid, xi64 + eps * v, rho, tau, G, g, steps, region)
+          - _oracle_loss(shape, solid, xi64 - eps * v, rho, tau, G, g, steps, region)) / (2 * eps)
+    assert float((grad * v).sum()) == pytest.approx(dd, rel=1e-3, abs=1e-3 * scale)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden finite differences not generated")
+def test_adjoint64_full_against_golden_fd():
+    """64^3 sphere pack, xi ~ U[-0.4, 0.4], 500 steps, checkpoint every 25;
+    20 voxels against FP64 oracle central differences stored by
+    tests/golden/make_adjoint64_fd.py."""
+    rec = json.load(open(GOLDEN))
+    w = wl.workload("adjoint64")
+    assert wl.sha256(w.solid) == rec["solid_sha256"] and wl.sha256(w.xi) == rec["xi_sha256"]
+    nx, ny, nz = w.shape
+    region = np.zeros((nz, ny, nx), np.uint8)
+    region[:, :, 3:nx - 3] = 1
+    print(f"[case] adjoint64 full steps={rec['steps']}", flush=True)
+    L, grad, _ = _gpu_gradient(w.shape, w.solid, w.xi, w.rho, w.tau, w.G, w.g, rec["steps"], 25, region)
+    assert L == pytest.approx(rec["loss"], rel=1e-5)
+    fd = np.array([v["fd"] for v in rec["voxels"]])
+    adj = np.array([grad[tuple(v["zyx"])] for v in rec["voxels"]])
+    scale = np.abs(fd).max()
+    err = np.abs(adj - fd).max() / scale
+    print(f"[adjoint64] max|fd|={scale:.3e} rel err={err:.3e}", flush=True)
+    for v, a in zip(rec["voxels"], adj):
+        print(f"   {v['zyx']} fd={v['fd']:.6e} adj={a:.6e}", flush=True)
+    assert err <= 1e-3
