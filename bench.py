@@ -83,6 +83,43 @@ def run_gpu(w, storage, steps, warmup):
     return res
 
 
+def run_adjoint(steps=500, every=25):
+    """Adjoint cost on the 64^3 adjoint workload: forward, forward with
+    checkpoints, and the reverse sweep (segment recompute included)."""
+    import torch
+    from paper_2207_01534_amd import workloads as wl
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams
+    w = wl.workload("adjoint64")
+    nx, ny, nz = w.shape
+    region = np.zeros((nz, ny, nx), np.uint8)
+    region[:, :, 3:nx - 3] = 1
+    reg = torch.as_tensor(region, device="cuda")
+    rho = torch.as_tensor(w.rho.astype(np.float32), device="cuda")
+    lat = Lattice(LatticeParams(shape=w.shape, tau=w.tau, G=w.G, g=w.g), torch.as_tensor(w.solid),
+                  torch.as_tensor(w.xi), rho)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    lat.step(20)                                           # warm-up
+    lat.init_equilibrium(rho)
+    _, t_fwd = timed(lambda: lat.step(steps))
+    lat.init_equilibrium(rho)
+    ck, t_fwd_ck = timed(lambda: lat.step_checkpointed(steps, every))
+    lat.gradient_snw(steps, every, ck, reg)                # warm-up (allocates the work buffer)
+    grad, t_bwd = timed(lambda: lat.gradient_snw(steps, every, ck, reg))
+    return {"workload": "adjoint64: 64^3 sphere pack r=6, porosity 0.40, xi~U[-0.4,0.4]",
+            "steps": steps, "every": every, "forward_ms": t_fwd * 1e3,
+            "forward_checkpointed_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
+            "cost_ratio": t_bwd / t_fwd, "cost_ratio_vs_checkpointed": t_bwd / t_fwd_ck,
+            "boundary_voxels": lat.boundary_count(),
+            "grad_abs_max": float(grad.abs().max())}
+
+
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2207_01534_amd", "csrc", "lbm_device.hpp"),
                   os.path.join(ROOT, "paper_2207_01534_amd", "csrc", "lbm_kernels.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_step_kernels_f32.json")
@@ -153,6 +190,7 @@ def main():
                     help="extra storage forms timed in the same run (comma list, '' for none)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB elementwise copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -182,6 +220,12 @@ def main():
         _log(f"timing variant {v}")
         variants[v] = run_gpu(w, v, args.steps, args.warmup)
         _log(f"{v}: {variants[v]['mlups']:.0f} MLUPS")
+
+    adjoint = None
+    if not args.no_adjoint:
+        _log("timing the adjoint (64^3, 500 steps, checkpoint every 25)")
+        adjoint = run_adjoint()
+        _log(f"adjoint: backward/forward = {adjoint['cost_ratio']:.2f}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -214,6 +258,7 @@ def main():
         "mflups": round(main_res["mflups"], 1),
         "gbs_alg_step": round(main_res["gbs_alg_step"], 1),
         "kernels_ms_avg": {k: round(v, 4) for k, v in main_res["kernels_ms_avg"].items()},
+        "adjoint": adjoint,
         "variants": {k: {"mlups": round(v["mlups"], 1), "mflups": round(v["mflups"], 1),
                          "ms_per_step": round(v["ms_per_step"], 4),
                          "gbs_alg_step": round(v["gbs_alg_step"], 1),
