@@ -48,7 +48,7 @@ def run_gpu(w, storage, steps, warmup):
     import torch
     from paper_2207_01534_amd.lattice import Lattice, LatticeParams, Storage
     st = {"f32": Storage.F32, "f16": Storage.F16, "bf16": Storage.BF16}[storage]
-    p = LatticeParams(shape=w.shape, tau=w.tau, G=w.G, g=w.g, storage=st)
+    p = LatticeParams(shape=w.shape, tau=w.tau, G=w.G, g=w.g, storage=st, fluid_capacity=w.n_fluid)
     lat = Lattice(p, torch.as_tensor(w.solid), torch.as_tensor(w.xi),
                   torch.as_tensor(w.rho.astype(np.float32)))
     lat.step(warmup)

@@ -77,7 +77,9 @@ typedef struct {
     uint32_t abi_version; /* must equal MCLBM_ABI_VERSION                         */
     int32_t nx, ny, nz;   /* lattice extents, each >= 3, nx*ny*nz < 2^30          */
     int32_t storage;      /* mclbm_storage                                        */
-    int32_t reserved;     /* must be 0                                            */
+    int32_t fluid_capacity; /* populations are stored for fluid voxels only; the
+                               workspace holds this many (0 = nx*ny*nz).
+                               set_geometry fails with EINVAL on more.            */
     double tau[2];        /* relaxation times tau^(1), tau^(2) > 0.5 (Eqs. 6-7)   */
     double G;             /* cohesion / adhesion strength G_coh (Eqs. 11, 13)     */
     double g[2][3];       /* body acceleration per component: F^b = rho g (Eq. 10) */
@@ -104,8 +106,15 @@ mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t 
  *          voxels that have a fluid neighbour; chi^(1) = 1 + xi,
  *          chi^(2) = 1 - xi.  |xi| < 1 required there (EINVAL otherwise).
  * Both are copied into the workspace; the caller may free them afterwards.
- * Synchronises the stream.  Resets the step counter to 0. */
+ * Builds the sparse storage: populations live only at fluid voxels,
+ * compacted within tiles of 64 x 4 voxels of one z plane; tiles without
+ * fluid are dropped.  Synchronises the stream.  Resets the step counter to
+ * 0.  On EINVAL (|xi| >= 1, or more fluid voxels than fluid_capacity) the
+ * lattice is left without geometry and set_geometry must be called again. */
 mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, const float* d_xi);
+
+/* Number of fluid voxels.  Valid after set_geometry. */
+mclbm_status mclbm_fluid_count(const mclbm_lattice* lat, int64_t* count);
 
 /* Number of solid voxels with at least one fluid neighbour (the voxels whose
  * xi matters and where gradients are non-zero).  Valid after set_geometry. */

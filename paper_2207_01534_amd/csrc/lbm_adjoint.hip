@@ -28,19 +28,21 @@ using CF = CodecF32;
 // Loss L = (1/|R|) sum_{fluid x in R} rho1 / (rho1 + rho2), FP64 partials.
 // ---------------------------------------------------------------------------
 template <bool ODD>
-__global__ __launch_bounds__(256) void k_loss_partial(Pops<CF> P, const uint32_t* __restrict__ nbm,
+__global__ __launch_bounds__(256) void k_loss_partial(Pops<CF> P, const int* __restrict__ fid,
+                                                      const uint32_t* __restrict__ nbm,
                                                       const uint8_t* __restrict__ region, Geo g,
                                                       double* __restrict__ partial) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
     double v = 0.0, c = 0.0;
-    if (x < g.nx) {
+    if (x < g.nx && y < g.ny) {
         const Nb nb(x, y, z, g);
         const uint32_t m = nbm[nb.idx];
         if (!(m & SELF_SOLID) && region[nb.idx]) {
             float f[2][Q];
-            load_node<CF>(f, P, nullptr, ODD, m, nb, g.np);
+            load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx],
+                               [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
             const double r0 = sum19(f[0]), r1 = sum19(f[1]);
             v = r0 / (r0 + r1);
             c = 1.0;
@@ -51,16 +53,17 @@ __global__ __launch_bounds__(256) void k_loss_partial(Pops<CF> P, const uint32_t
         c += __shfl_xor(c, off);
     }
     __shared__ double red[4][2];
-    if ((threadIdx.x & 63) == 0) {
-        red[threadIdx.x >> 6][0] = v;
-        red[threadIdx.x >> 6][1] = c;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    if ((tid & 63) == 0) {
+        red[tid >> 6][0] = v;
+        red[tid >> 6][1] = c;
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
+    if (tid < 2) {
         double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
+        for (int w = 0; w < 4; ++w) s += red[w][tid];
         const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        partial[(size_t)b * 2 + threadIdx.x] = s;
+        partial[(size_t)b * 2 + tid] = s;
     }
 }
 
@@ -93,14 +96,15 @@ __global__ void k_loss_final(const double* __restrict__ partial, int nblocks, do
 // as lambda_loc = 0 plus rhobar = (rho2, -rho1) / (rho1+rho2)^2 / |R|.
 // ---------------------------------------------------------------------------
 template <bool ODD>
-__global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const uint32_t* __restrict__ nbm,
+__global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const int* __restrict__ fid,
+                                                  const uint32_t* __restrict__ nbm,
                                                   const uint8_t* __restrict__ region, Geo g,
                                                   const double* __restrict__ loss, float* __restrict__ lam,
                                                   float2* __restrict__ rbar) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
-    if (x >= g.nx) return;
+    if (x >= g.nx || y >= g.ny) return;
     const Nb nb(x, y, z, g);
     const size_t n = (size_t)g.n;
     for (int k = 0; k < 2 * Q; ++k) lam[k * n + nb.idx] = 0.0f;
@@ -108,7 +112,8 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const uint32_t* __
     float2 r = make_float2(0.f, 0.f);
     if (!(m & SELF_SOLID) && region[nb.idx] && loss[1] > 0) {
         float f[2][Q];
-        load_node<CF>(f, P, nullptr, ODD, m, nb, g.np);
+        load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx],
+                           [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
         const double r0 = sum19(f[0]), r1 = sum19(f[1]);
         const double rt = r0 + r1;
         const double s = 1.0 / (rt * rt * loss[1]);
@@ -121,16 +126,17 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const uint32_t* __
 // A1: adjoint of streaming and of the local collision at fluid nodes.
 // ---------------------------------------------------------------------------
 template <bool ODD>
-__global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const uint32_t* __restrict__ nbm,
+__global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __restrict__ fid,
+                                                     const uint32_t* __restrict__ nbm,
                                                      const float2* __restrict__ psi,
                                                      const float* __restrict__ lam_next,
                                                      const float2* __restrict__ rbar_next,
                                                      float* __restrict__ lam_cur, float* __restrict__ abar,
                                                      Geo g, Phys ph) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
-    if (x >= g.nx) return;
+    if (x >= g.nx || y >= g.ny) return;
     const Nb nb(x, y, z, g);
     const size_t n = (size_t)g.n;
     const uint32_t m = nbm[nb.idx];
@@ -140,7 +146,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const uint32_t*
     }
     // forward quantities of this node at time t
     float f[2][Q];
-    load_node<CF>(f, P, nullptr, ODD, m, nb, g.np);
+    load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx], [&](int i, int s) { return fid[nb.at(i, s)]; },
+                       g.np);
     const float rho[2] = {sum19(f[0]), sum19(f[1])};
     float A[2][3];
     psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, A);
@@ -314,9 +321,9 @@ __global__ __launch_bounds__(256) void k_adj_rho(const uint32_t* __restrict__ nb
                                                  const float2* __restrict__ nbar, Geo g,
                                                  float2* __restrict__ rbar) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
-    if (x >= g.nx) return;
+    if (x >= g.nx || y >= g.ny) return;
     const Nb nb(x, y, z, g);
     const uint32_t m = nbm[nb.idx];
     if (m & SELF_SOLID) return;
@@ -345,38 +352,40 @@ __global__ void k_grad_scatter(const int* __restrict__ list, int count, const do
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-static dim3 rows(const Geo& g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
+// 64 x 4 blocks over (x, y), one z plane per grid row
+static dim3 rows(const Geo& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
+static const dim3 kBlock(64, 4);
 
 int loss_blocks(const Geo& g) {
     const dim3 r = rows(g);
     return (int)(r.x * r.y * r.z);
 }
 
-void launch_loss(const Pops<CF>& P, const uint32_t* nbm, const uint8_t* region, const Geo& g, int odd,
-                 double* partial, double* out, hipStream_t s) {
+void launch_loss(const Pops<CF>& P, const int* fid, const uint32_t* nbm, const uint8_t* region, const Geo& g,
+                 int odd, double* partial, double* out, hipStream_t s) {
     if (odd)
-        hipLaunchKernelGGL(k_loss_partial<true>, rows(g), dim3(256), 0, s, P, nbm, region, g, partial);
+        hipLaunchKernelGGL(k_loss_partial<true>, rows(g), kBlock, 0, s, P, fid, nbm, region, g, partial);
     else
-        hipLaunchKernelGGL(k_loss_partial<false>, rows(g), dim3(256), 0, s, P, nbm, region, g, partial);
+        hipLaunchKernelGGL(k_loss_partial<false>, rows(g), kBlock, 0, s, P, fid, nbm, region, g, partial);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, s, (const double*)partial, loss_blocks(g), out);
 }
 
-void launch_adj_seed(const Pops<CF>& P, const uint32_t* nbm, const uint8_t* region, const Geo& g, int odd,
-                     const double* loss, float* lam, float2* rbar, hipStream_t s) {
+void launch_adj_seed(const Pops<CF>& P, const int* fid, const uint32_t* nbm, const uint8_t* region, const Geo& g,
+                     int odd, const double* loss, float* lam, float2* rbar, hipStream_t s) {
     if (odd)
-        hipLaunchKernelGGL(k_adj_seed<true>, rows(g), dim3(256), 0, s, P, nbm, region, g, loss, lam, rbar);
+        hipLaunchKernelGGL(k_adj_seed<true>, rows(g), kBlock, 0, s, P, fid, nbm, region, g, loss, lam, rbar);
     else
-        hipLaunchKernelGGL(k_adj_seed<false>, rows(g), dim3(256), 0, s, P, nbm, region, g, loss, lam, rbar);
+        hipLaunchKernelGGL(k_adj_seed<false>, rows(g), kBlock, 0, s, P, fid, nbm, region, g, loss, lam, rbar);
 }
 
-void launch_adj_collide(const Pops<CF>& P, const uint32_t* nbm, const float2* psi, const float* lam_next,
-                        const float2* rbar_next, float* lam_cur, float* abar, const Geo& g, const Phys& ph,
-                        int odd, hipStream_t s) {
+void launch_adj_collide(const Pops<CF>& P, const int* fid, const uint32_t* nbm, const float2* psi,
+                        const float* lam_next, const float2* rbar_next, float* lam_cur, float* abar, const Geo& g,
+                        const Phys& ph, int odd, hipStream_t s) {
     if (odd)
-        hipLaunchKernelGGL(k_adj_collide<true>, rows(g), dim3(256), 0, s, P, nbm, psi, lam_next, rbar_next,
+        hipLaunchKernelGGL(k_adj_collide<true>, rows(g), kBlock, 0, s, P, fid, nbm, psi, lam_next, rbar_next,
                            lam_cur, abar, g, ph);
     else
-        hipLaunchKernelGGL(k_adj_collide<false>, rows(g), dim3(256), 0, s, P, nbm, psi, lam_next, rbar_next,
+        hipLaunchKernelGGL(k_adj_collide<false>, rows(g), kBlock, 0, s, P, fid, nbm, psi, lam_next, rbar_next,
                            lam_cur, abar, g, ph);
 }
 
@@ -389,7 +398,7 @@ void launch_adj_ivsd(const int* list, const float* xil, int count, const uint32_
 
 void launch_adj_rho(const uint32_t* nbm, const float* abar, const float2* nbar, const Geo& g, float2* rbar,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_rho, rows(g), dim3(256), 0, s, nbm, abar, nbar, g, rbar);
+    hipLaunchKernelGGL(k_adj_rho, rows(g), kBlock, 0, s, nbm, abar, nbar, g, rbar);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {

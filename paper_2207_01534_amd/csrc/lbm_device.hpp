@@ -35,7 +35,7 @@ constexpr uint32_t NB_BITS = ((1u << Q) - 1u) & ~1u;
 struct Geo {
     int nx, ny, nz;
     int n;   // nx * ny * nz (< 2^30, so byte offsets of a plane fit in 32 bits)
-    int np;  // population plane stride in elements (>= n)
+    int np;  // population plane stride in elements (>= the fluid capacity)
 };
 
 // Loads and stores at a 32-bit element offset from a wave-uniform base, so
@@ -121,7 +121,8 @@ __device__ __forceinline__ float inv_total(float2 r) {
 }
 
 // Population storage: 36 moving planes of T (component-major, directions
-// 1..18) and 2 FP32 rest planes, each plane np elements long.
+// 1..18) and 2 FP32 rest planes, each plane np elements long and indexed by
+// fluid id.
 template <class C>
 struct Pops {
     typename C::T* mv;
@@ -132,35 +133,43 @@ struct Pops {
 };
 
 // ---------------------------------------------------------------------------
-// AA-pattern single-buffer streaming with halfway bounce-back through ghost
-// slots.  The state at an even time level keeps f_i(x) in slot (i, x); at an
-// odd level f_i(x) sits in slot (opp i, x - e_i).
-//   even step at fluid x: read slots (i, x); write f*_i(x) to (opp i, x), and
-//     also to the ghost slot (i, x + e_i) when x + e_i is solid;
-//   odd step at fluid x:  read slots (opp i, x - e_i) -- a solid x - e_i holds
-//     the ghost copy of f*_(opp i)(x), i.e. the bounced population; write
-//     f*_i(x) to (i, x + e_i), and also to (opp i, x) when x + e_i is solid
-//     (the bounced population the next even step reads at home).
-// Every slot a thread reads or writes belongs to it alone within a step (a
-// solid node's slot (i, s) is reached only from the fluid node s - e_i), so
-// the update is race-free in place, and no read needs a bounce-back branch.
-// The node whose density normalised the value read as f_i(x) is x - e_i if
-// that node is fluid and x itself otherwise, in both parities.
+// Tile-sparse AA-pattern streaming with halfway bounce-back.
+// Only fluid nodes own populations: fluid node k (its fluid id) owns slots
+// (i, k) of the 38 planes.  The state at an even time level keeps f_i(x) in
+// slot (i, k(x)); at an odd level f_i(x) sits in slot (opp i, k(x - e_i)) if
+// x - e_i is fluid and in (i, k(x)) otherwise (the bounced population).
+//   even step at fluid x: read slots (i, k); write f*_i(x) to (opp i, k);
+//   odd step at fluid x:  read (opp i, k(x - e_i)) or, across a wall, (i, k);
+//     write f*_i(x) to (i, k(x + e_i)) or, across a wall, to (opp i, k).
+// Each thread reads exactly the slots it later writes, so the update is
+// race-free in place, and an even step touches no other node's slots.  The
+// same code runs out of place (separate source and destination buffers).
+// The node whose density normalised the value read as f_i(x) (F16/BF16) is
+// x - e_i if that node is fluid and x itself otherwise, in both parities.
+// FidAt(i, s) returns the fluid id of x + s e_i, or -1 if it is solid.
 // ---------------------------------------------------------------------------
 
-// Load and decode the 19 incoming populations of both components at a fluid
-// node.  rprev: densities of the previous time level (F16/BF16 codecs only).
-template <class C>
+// Load and decode the 19 incoming populations of both components at fluid
+// node k.  rprev: densities of the previous time level (F16/BF16 only);
+// nbm: the node's neighbourhood word (F16/BF16 only).
+template <class C, bool ODD, class FidAt>
 __device__ __forceinline__ void load_node(float (&f)[2][Q], const Pops<C>& P, const float2* rprev,
-                                          bool odd, uint32_t nbm, const Nb& nb, int np) {
-    f[0][0] = ld(P.rest, nb.idx);
-    f[1][0] = ld(P.rest + np, nb.idx);
+                                          uint32_t nbm, const Nb& nb, uint32_t k, FidAt fid_at, int np) {
+    f[0][0] = ld(P.rest, k);
+    f[1][0] = ld(P.rest + np, k);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int dir = odd ? opp(i) : i;
-        const uint32_t at = odd ? nb.at(i, -1) : nb.idx;
-        const typename C::T h0 = ld(P.plane(0, dir, np), at);
-        const typename C::T h1 = ld(P.plane(1, dir, np), at);
+        typename C::T h0, h1;
+        if constexpr (!ODD) {
+            h0 = ld(P.plane(0, i, np), k);
+            h1 = ld(P.plane(1, i, np), k);
+        } else {
+            const int src = fid_at(i, -1);
+            const bool wall = src < 0;
+            const uint32_t at = wall ? k : (uint32_t)src;
+            h0 = ld(wall ? P.plane(0, i, np) : P.plane(0, opp(i), np), at);
+            h1 = ld(wall ? P.plane(1, i, np) : P.plane(1, opp(i), np), at);
+        }
         if constexpr (C::kRef) {
             const bool src_solid = (nbm >> opp(i)) & 1u;
             const float2 rw = ld(rprev, src_solid ? nb.idx : nb.at(i, -1));
@@ -183,7 +192,7 @@ __device__ __forceinline__ float sum19(const float (&f)[Q]) {
     return a;
 }
 
-// Encode and store the post-collision moving populations of one fluid node;
+// Encode and store the post-collision moving populations of fluid node k;
 // the rest population is set from the node's mass balance,
 //   f*_0 = rho - sum_{i>=1} decode(encode(f*_i)),
 // which equals the collided rest population in exact arithmetic (the
@@ -193,9 +202,9 @@ __device__ __forceinline__ float sum19(const float (&f)[Q]) {
 // populations is absorbed by the FP32 rest population.
 // mass: incoming component densities; rho_ref: this node's density as the
 // decoder will read it next step (F16/BF16 codecs only).
-template <class C>
-__device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C>& P, const float (&mass)[2],
-                                           float2 rho_ref, bool odd, uint32_t nbm, const Nb& nb, int np) {
+template <class C, bool ODD, class FidAt>
+__device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C>& D, const float (&mass)[2],
+                                           float2 rho_ref, uint32_t k, FidAt fid_at, int np) {
     float sum0 = 0.0f, sum1 = 0.0f;
     const float inv_t = C::kRef ? inv_total(rho_ref) : 0.0f;
     const float rt = rho_ref.x + rho_ref.y;
@@ -203,29 +212,21 @@ __device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C
     for (int i = 1; i < Q; ++i) {
         const typename C::T h0 = C::enc(fs[0][i], weight(i), rho_ref.x, inv_t);
         const typename C::T h1 = C::enc(fs[1][i], weight(i), rho_ref.y, inv_t);
-        const bool nb_solid = (nbm >> i) & 1u;
-        if (!odd) {
-            st(P.plane(0, opp(i), np), nb.idx, h0);
-            st(P.plane(1, opp(i), np), nb.idx, h1);
-            if (nb_solid) {  // ghost copy for the odd step's reads
-                const uint32_t s = nb.at(i, +1);
-                st(P.plane(0, i, np), s, h0);
-                st(P.plane(1, i, np), s, h1);
-            }
+        if constexpr (!ODD) {
+            st(D.plane(0, opp(i), np), k, h0);
+            st(D.plane(1, opp(i), np), k, h1);
         } else {
-            const uint32_t d = nb.at(i, +1);
-            st(P.plane(0, i, np), d, h0);
-            st(P.plane(1, i, np), d, h1);
-            if (nb_solid) {  // bounced population, read at home by the next even step
-                st(P.plane(0, opp(i), np), nb.idx, h0);
-                st(P.plane(1, opp(i), np), nb.idx, h1);
-            }
+            const int dst = fid_at(i, +1);
+            const bool wall = dst < 0;
+            const uint32_t at = wall ? k : (uint32_t)dst;
+            st(wall ? D.plane(0, opp(i), np) : D.plane(0, i, np), at, h0);
+            st(wall ? D.plane(1, opp(i), np) : D.plane(1, i, np), at, h1);
         }
         sum0 += C::dec(h0, weight(i), rho_ref.x, rt);
         sum1 += C::dec(h1, weight(i), rho_ref.y, rt);
     }
-    st(P.rest, nb.idx, mass[0] - sum0);
-    st(P.rest + np, nb.idx, mass[1] - sum1);
+    st(D.rest, k, mass[0] - sum0);
+    st(D.rest + np, k, mass[1] - sum1);
 }
 
 // Physical parameters in FP32.

@@ -1,8 +1,11 @@
 // HIP kernels of the two-component D3Q19 pseudopotential step (gfx950).
 //
-// One time step is three launches on the caller's stream:
+// Populations are stored only for fluid nodes, compacted within tiles of
+// 64 x 4 nodes of one z plane; tiles without fluid are dropped (the paper's
+// sparse tiling, Sec. 5, with node compaction inside each tile).  One time
+// step is three launches on the caller's stream:
 //   k_density        rho^(sigma) at every fluid node from the incoming
-//                    populations (Eq. 3); 0 at solid nodes.
+//                    populations (Eq. 3), written to the dense psi-hat field.
 //   k_ivsd           virtual solid densities at the solid nodes that touch
 //                    fluid (Eqs. 14-15), over a compact list; together with
 //                    k_density this fills the unified pseudopotential psi-hat.
@@ -47,8 +50,9 @@ __global__ void k_boundary_count(const uint32_t* __restrict__ nbm, int n, int* _
     if (threadIdx.x == 0) counts[blockIdx.x] = c;
 }
 
-// Exclusive scan of the per-block counts by one block (set-up only).
-__global__ void k_boundary_scan(int* __restrict__ counts, int nblocks, int* __restrict__ total) {
+// Exclusive scan of an int array in place by one block (set-up only); the
+// total goes to total[0].
+__global__ void k_scan(int* __restrict__ counts, int nblocks, int* __restrict__ total) {
     __shared__ int part[1024];
     const int t = threadIdx.x;
     const int per = (nblocks + 1023) / 1024;
@@ -73,25 +77,39 @@ __global__ void k_boundary_scan(int* __restrict__ counts, int nblocks, int* __re
     if (t == 1023) total[0] = part[1023];
 }
 
+// Rank of this thread's flag among the flagged threads of its block
+// (ordered by linear thread id); the block's flagged count goes to *count.
+__device__ __forceinline__ int block_rank(bool flag, int* wave_off, int* count) {
+    const unsigned long long ball = __ballot(flag);
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int rank = __popcll(ball & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_off[wave] = __popcll(ball);
+    __syncthreads();
+    int base = 0, all = 0;
+    const int nw = (int)(blockDim.x * blockDim.y) >> 6;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) base += wave_off[w];
+        all += wave_off[w];
+    }
+    *count = all;
+    return base + rank;
+}
+
 __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* __restrict__ xi,
                                  int n, const int* __restrict__ offsets, int* __restrict__ list,
                                  float* __restrict__ xil, int* __restrict__ bad) {
     __shared__ int wave_off[kListBlock / 64];
     const int idx = blockIdx.x * kListBlock + threadIdx.x;
     const bool flag = idx < n && is_boundary_solid(nbm[idx]);
-    const unsigned long long ball = __ballot(flag);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int rank = __popcll(ball & ((1ull << lane) - 1ull));
-    if (lane == 0) wave_off[wave] = __popcll(ball);
-    __syncthreads();
-    int base = offsets[blockIdx.x];
-    for (int w = 0; w < wave; ++w) base += wave_off[w];
+    int cnt;
+    const int rank = block_rank(flag, wave_off, &cnt);
     bool invalid = false;
     if (flag) {
         const float v = xi[idx];
-        list[base + rank] = idx;
-        xil[base + rank] = v;
+        const int at = offsets[blockIdx.x] + rank;
+        list[at] = idx;
+        xil[at] = v;
         invalid = !(fabsf(v) < 1.0f);
     }
     const int any_bad = __syncthreads_or(invalid);
@@ -99,11 +117,59 @@ __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* 
 }
 
 // ---------------------------------------------------------------------------
+// Tiles: 64 x 4 nodes of one z plane, numbered x fastest, then y, then z.
+// ---------------------------------------------------------------------------
+constexpr int TX = 64, TY = 4;
+constexpr int HX = TX + 2, HY = TY + 2;
+
+__device__ __forceinline__ void tile_origin(int t, const Geo& g, int& x0, int& y0, int& z) {
+    const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
+    x0 = (t % ntx) * TX;
+    y0 = ((t / ntx) % nty) * TY;
+    z = t / (ntx * nty);
+}
+
+// Per tile: number of fluid nodes (into cnt and, for the scans, into base
+// and active_flag).
+__global__ void k_tile_count(const uint32_t* __restrict__ nbm, Geo g, int* __restrict__ cnt,
+                             int* __restrict__ base, int* __restrict__ active_flag) {
+    int x0, y0, z;
+    tile_origin(blockIdx.x, g, x0, y0, z);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    const bool fluid = x < g.nx && y < g.ny && !(nbm[x + g.nx * (y + g.ny * z)] & SELF_SOLID);
+    const int c = __syncthreads_count(fluid);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        cnt[blockIdx.x] = c;
+        base[blockIdx.x] = c;
+        active_flag[blockIdx.x] = c > 0 ? 1 : 0;
+    }
+}
+
+// Fluid ids (tile base + rank inside the tile, x fastest), the dense id map
+// (-1 at solid) and each fluid node's position inside its tile.
+__global__ void k_tile_ids(const uint32_t* __restrict__ nbm, Geo g, const int* __restrict__ base,
+                           const int* __restrict__ cnt, const int* __restrict__ active_pos,
+                           int* __restrict__ fid, uint8_t* __restrict__ loc, int* __restrict__ active) {
+    __shared__ int wave_off[TX * TY / 64];
+    int x0, y0, z;
+    tile_origin(blockIdx.x, g, x0, y0, z);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    const bool inside = x < g.nx && y < g.ny;
+    const int idx = x + g.nx * (y + g.ny * z);
+    const bool fluid = inside && !(nbm[idx] & SELF_SOLID);
+    int c;
+    const int rank = block_rank(fluid, wave_off, &c);
+    if (inside) fid[idx] = fluid ? base[blockIdx.x] + rank : -1;
+    if (fluid) loc[base[blockIdx.x] + rank] = (uint8_t)(threadIdx.x + TX * threadIdx.y);
+    if (threadIdx.x == 0 && threadIdx.y == 0 && cnt[blockIdx.x] > 0) active[active_pos[blockIdx.x]] = blockIdx.x;
+}
+
+// ---------------------------------------------------------------------------
 // Initial state f_i = w_i rho (fluid at rest), even-parity layout.
 // ---------------------------------------------------------------------------
 template <class C>
-__global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const float* __restrict__ rho_in,
-                       float2* __restrict__ rprev, Geo g) {
+__global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* __restrict__ fid,
+                       const float* __restrict__ rho_in, float2* __restrict__ rprev, Geo g) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const int z = blockIdx.z;
@@ -115,6 +181,7 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const float*
         rprev[self] = make_float2(0.f, 0.f);
         return;
     }
+    const uint32_t k = (uint32_t)fid[self];
     const float r0 = rho_in[self], r1 = rho_in[(size_t)g.n + self];
     rprev[self] = make_float2(r0, r1);
     float sum0 = 0.f, sum1 = 0.f;
@@ -124,7 +191,7 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const float*
         typename C::T h0, h1;
         if constexpr (C::kRef) {
             // reference densities of the node recorded as the writer of
-            // slot (i, x): x - e_i if fluid, else x
+            // slot (i, k): x - e_i if fluid, else x
             const bool src_solid = (m >> opp(i)) & 1u;
             const uint32_t w = src_solid ? self : nb.at(i, -1);
             const float2 rw = src_solid ? make_float2(r0, r1) : make_float2(rho_in[w], rho_in[(size_t)g.n + w]);
@@ -140,65 +207,79 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const float*
             sum0 += C::dec(h0, weight(i), 0.f, 0.f);
             sum1 += C::dec(h1, weight(i), 0.f, 0.f);
         }
-        st(P.plane(0, i, g.np), self, h0);
-        st(P.plane(1, i, g.np), self, h1);
+        st(P.plane(0, i, g.np), k, h0);
+        st(P.plane(1, i, g.np), k, h1);
     }
     // rest population from the node mass (see store_node)
-    st(P.rest, self, r0 - sum0);
-    st(P.rest + g.np, self, r1 - sum1);
+    st(P.rest, k, r0 - sum0);
+    st(P.rest + g.np, k, r1 - sum1);
 }
 
 // ---------------------------------------------------------------------------
-// Tiles of 64 x 4 nodes in one z plane.  Blocks are numbered on a 1D grid and
+// Tile kernels.  One block of 256 threads per active tile; thread j < count
+// handles the tile's j-th fluid node.  Blocks are numbered on a 1D grid and
 // mapped XCD-aware: the hardware deals consecutive block ids round-robin to
-// the 8 XCDs, so block b takes tile (b mod 8) * per + b / 8 and every XCD
-// works through a contiguous run of neighbouring tiles, whose shared halo
-// rows then hit in that XCD's L2.
+// the 8 XCDs, so block b takes active tile (b mod 8) * per + b / 8 and each
+// XCD works through a contiguous run of neighbouring tiles, whose shared
+// halo rows then hit in that XCD's L2.
 // ---------------------------------------------------------------------------
-constexpr int TX = 64, TY = 4;
-constexpr int HX = TX + 2, HY = TY + 2;
-
-struct TileGrid {
-    int ntx, nty, ntiles, grid;
-};
-
-__device__ __forceinline__ bool tile_of_block(const TileGrid& T, int& bx, int& by, int& bz) {
+__device__ __forceinline__ int active_of_block(int nactive) {
     const int per = gridDim.x >> 3;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= T.ntiles) return false;
-    bx = tile % T.ntx;
-    by = (tile / T.ntx) % T.nty;
-    bz = tile / (T.ntx * T.nty);
-    return true;
+    const int a = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    return a < nactive ? a : -1;
 }
 
-// ---------------------------------------------------------------------------
-// K1: densities.  psi[x] = (rho1, rho2) at fluid nodes, (0, 0) at solid.
-// ---------------------------------------------------------------------------
-template <class C, bool ODD>
-__global__ __launch_bounds__(TX * TY) void k_density(Pops<C> P, const uint32_t* __restrict__ nbm,
-                                                     const float2* __restrict__ rprev,
-                                                     float2* __restrict__ psi, Geo g, TileGrid T) {
-    int bx, by, z;
-    if (!tile_of_block(T, bx, by, z)) return;
-    const int x = bx * TX + threadIdx.x, y = by * TY + threadIdx.y;
-    if (x >= g.nx || y >= g.ny) return;
-    const Nb nb(x, y, z, g);
-    const uint32_t m = ld(nbm, nb.idx);
-    if (m & SELF_SOLID) {
-        st(psi, nb.idx, make_float2(0.f, 0.f));
-        return;
+// Stage values of planes z-1, z, z+1 over the tile plus a one-node halo.
+template <class T, class Src>
+__device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, int z, const Geo& g, Src src,
+                                           T fill) {
+    const int nxy = g.nx * g.ny;
+    const int zs[3] = {(z == 0 ? g.nz - 1 : z - 1) * nxy, z * nxy, (z == g.nz - 1 ? 0 : z + 1) * nxy};
+    for (int k = threadIdx.x; k < 3 * HX * HY; k += TX * TY) {
+        const int pl = k / (HX * HY);
+        const int r = k - pl * (HX * HY);
+        const int hy = r / HX, hx = r - hy * HX;
+        int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+        gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+        T v = fill;
+        if (gx < g.nx && gy < g.ny) v = src((uint32_t)(gx + g.nx * gy + zs[pl]));
+        tile[pl][hy][hx] = v;
     }
+}
+
+// K1: densities.  psi[x] = (rho1, rho2) at fluid nodes.
+template <class C, bool ODD>
+__global__ __launch_bounds__(TX * TY) void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm,
+                                                     const float2* __restrict__ rprev,
+                                                     float2* __restrict__ psi, Geo g) {
+    const int a = active_of_block(S.nactive);
+    if (a < 0) return;
+    const int t = S.active[a];
+    int x0, y0, z;
+    tile_origin(t, g, x0, y0, z);
+    const int base = S.base[t], count = S.count[t];
+    __shared__ int fidt[ODD ? 3 : 1][HY][HX];
+    if constexpr (ODD) {
+        stage_halo(fidt, x0, y0, z, g, [&](uint32_t i) { return S.fid[i]; }, -1);
+        __syncthreads();
+    }
+    const int j = threadIdx.x;
+    if (j >= count) return;
+    const uint32_t k = (uint32_t)(base + j);
+    const int p = S.loc[k];
+    const int lx = p & (TX - 1), ly = p / TX;
+    const Nb nb(x0 + lx, y0 + ly, z, g);
+    const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
     float f[2][Q];
-    load_node<C>(f, P, rprev, ODD, m, nb, g.np);
+    auto fid_at = [&](int i, int s) { return fidt[1 + s * DZ[i]][1 + ly + s * DY[i]][1 + lx + s * DX[i]]; };
+    load_node<C, ODD>(f, P, rprev, m, nb, k, fid_at, g.np);
     st(psi, nb.idx, make_float2(sum19(f[0]), sum19(f[1])));
 }
 
-// ---------------------------------------------------------------------------
 // K1b: IVSD virtual solid density at boundary solid nodes (Eqs. 14-15):
 // rho~^(s) = chi^(s) sum_i w_i rho^(s)(x+e_i) [fluid] / sum_i w_i [fluid],
 // chi^(1) = 1 + xi, chi^(2) = 1 - xi.
-// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, const float* __restrict__ xil,
                                               int count, const uint32_t* __restrict__ nbm,
                                               float2* __restrict__ psi, Geo g) {
@@ -225,66 +306,57 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
     psi[idx] = make_float2((1.0f + v) * n0 * inv, (1.0f - v) * n1 * inv);
 }
 
-// ---------------------------------------------------------------------------
-// K2: fused force + collision + streaming, one 64 x 4 tile of one z plane per
-// block.  The psi-hat values of planes z-1, z, z+1 over the tile and a
-// one-node halo are staged in LDS once (one barrier); each fluid node then
-// reads its 18 neighbours from LDS.  P is the state read, D the state
-// written: the same buffer for the in-place step, two buffers when a step is
-// recomputed into a separate slot (the AA addressing writes every slot the
-// next step reads, so an out-of-place step produces a complete state).
-// ---------------------------------------------------------------------------
+// K2: fused force + collision + streaming for the fluid nodes of one tile.
+// The psi-hat values (and, in odd steps, the fluid ids) of planes z-1, z,
+// z+1 over the tile and a one-node halo are staged in LDS behind one
+// barrier; each node then reads its 18 neighbours from LDS.  P is the state
+// read, D the state written: the same buffer for the in-place step, two
+// buffers when a step is recomputed into a separate slot.
 template <class C, bool ODD>
-__global__ __launch_bounds__(TX * TY) void k_collide_stream(
-    Pops<C> P, Pops<C> D, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
-    const float2* __restrict__ psi, Geo g, Phys ph, TileGrid T) {
-    int bx, by, z;
-    if (!tile_of_block(T, bx, by, z)) return;
-    const int x0 = bx * TX, y0 = by * TY;
-
-    __shared__ float2 tile[3][HY][HX];
-    {
-        const int nxy = g.nx * g.ny;
-        const int zs[3] = {(z == 0 ? g.nz - 1 : z - 1) * nxy, z * nxy, (z == g.nz - 1 ? 0 : z + 1) * nxy};
-        for (int k = threadIdx.y * TX + threadIdx.x; k < 3 * HX * HY; k += TX * TY) {
-            const int pl = k / (HX * HY);
-            const int r = k - pl * (HX * HY);
-            const int hy = r / HX, hx = r - hy * HX;
-            int gx = x0 + hx - 1, gy = y0 + hy - 1;
-            gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
-            gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-            float2 v = make_float2(0.f, 0.f);
-            if (gx < g.nx && gy < g.ny) v = ld(psi, (uint32_t)(gx + g.nx * gy + zs[pl]));
-            tile[pl][hy][hx] = v;
-        }
-    }
+__global__ __launch_bounds__(TX * TY) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
+                                                            const uint32_t* __restrict__ nbm,
+                                                            const float2* __restrict__ rprev,
+                                                            const float2* __restrict__ psi, Geo g, Phys ph) {
+    const int a = active_of_block(S.nactive);
+    if (a < 0) return;
+    const int t = S.active[a];
+    int x0, y0, z;
+    tile_origin(t, g, x0, y0, z);
+    const int base = S.base[t], count = S.count[t];
+    __shared__ float2 psit[3][HY][HX];
+    __shared__ int fidt[ODD ? 3 : 1][HY][HX];
+    stage_halo(psit, x0, y0, z, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
+    if constexpr (ODD) stage_halo(fidt, x0, y0, z, g, [&](uint32_t i) { return S.fid[i]; }, -1);
     __syncthreads();
-
-    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-    if (x >= g.nx || y >= g.ny) return;
-    const Nb nb(x, y, z, g);
-    const uint32_t m = ld(nbm, nb.idx);
-    if (m & SELF_SOLID) return;
+    const int j = threadIdx.x;
+    if (j >= count) return;
+    const uint32_t k = (uint32_t)(base + j);
+    const int p = S.loc[k];
+    const int lx = p & (TX - 1), ly = p / TX;
+    const Nb nb(x0 + lx, y0 + ly, z, g);
+    const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
+    auto fid_at = [&](int i, int s) { return fidt[1 + s * DZ[i]][1 + ly + s * DY[i]][1 + lx + s * DX[i]]; };
 
     float f[2][Q];
-    load_node<C>(f, P, rprev, ODD, m, nb, g.np);
+    load_node<C, ODD>(f, P, rprev, m, nb, k, fid_at, g.np);
     const float rho[2] = {sum19(f[0]), sum19(f[1])};
-    const int tx = threadIdx.x + 1, ty = threadIdx.y + 1;
+    const int tx = lx + 1, ty = ly + 1;
     float acc[2][3];
-    psi_sum([&](int i) { return tile[1 + DZ[i]][ty + DY[i]][tx + DX[i]]; }, acc);
+    psi_sum([&](int i) { return psit[1 + DZ[i]][ty + DY[i]][tx + DX[i]]; }, acc);
     float F[2][3];
     total_force(rho, acc, ph, F);
     float u[3];
     collide(f, rho, F, ph, u);
-    store_node<C>(f, D, rho, tile[1][ty][tx], ODD, m, nb, g.np);
+    store_node<C, ODD>(f, D, rho, psit[1][ty][tx], k, fid_at, g.np);
 }
 
 // ---------------------------------------------------------------------------
 // Readouts and diagnostics at the current time level (psi already filled by
-// k_density + k_ivsd for this level).
+// k_density + k_ivsd for this level).  Dense over all nodes.
 // ---------------------------------------------------------------------------
 template <class C, bool ODD>
-__global__ __launch_bounds__(TX * TY) void k_fields(Pops<C> P, const uint32_t* __restrict__ nbm,
+__global__ __launch_bounds__(TX * TY) void k_fields(Pops<C> P, const int* __restrict__ fid,
+                                                    const uint32_t* __restrict__ nbm,
                                                     const float2* __restrict__ rprev,
                                                     const float2* __restrict__ psi, Geo g, Phys ph,
                                                     float* __restrict__ o_rho, float* __restrict__ o_u,
@@ -304,7 +376,8 @@ __global__ __launch_bounds__(TX * TY) void k_fields(Pops<C> P, const uint32_t* _
         float pr = 0.f;
         if (!(m & SELF_SOLID)) {
             float f[2][Q];
-            load_node<C>(f, P, rprev, ODD, m, nb, g.np);
+            load_node<C, ODD>(f, P, rprev, m, nb, (uint32_t)fid[self],
+                              [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
             rho[0] = sum19(f[0]);
             rho[1] = sum19(f[1]);
             float acc[2][3];
@@ -394,14 +467,7 @@ void launch_store_words(uint64_t* dst, const uint64_t (&w)[4], hipStream_t s) {
 static dim3 row_grid(const Geo& g) { return dim3((g.nx + 63) / 64, g.ny, g.nz); }
 static dim3 tile_grid3(const Geo& g) { return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz); }
 
-static TileGrid tiles(const Geo& g) {
-    TileGrid T;
-    T.ntx = (g.nx + TX - 1) / TX;
-    T.nty = (g.ny + TY - 1) / TY;
-    T.ntiles = T.ntx * T.nty * g.nz;
-    T.grid = ((T.ntiles + 7) / 8) * 8;
-    return T;
-}
+int tile_count(const Geo& g) { return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * g.nz; }
 
 void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hipStream_t s) {
     hipLaunchKernelGGL(k_neighbour_bits, row_grid(g), dim3(64), 0, s, solid, nbm, g);
@@ -413,25 +479,43 @@ void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int
                           float* xil, int* bad, const Geo& g, hipStream_t s) {
     const int nb = boundary_blocks(g);
     hipLaunchKernelGGL(k_boundary_count, dim3(nb), dim3(kListBlock), 0, s, nbm, g.n, counts);
-    hipLaunchKernelGGL(k_boundary_scan, dim3(1), dim3(1024), 0, s, counts, nb, total);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, nb, total);
     hipLaunchKernelGGL(k_boundary_write, dim3(nb), dim3(kListBlock), 0, s, nbm, xi, g.n,
                        (const int*)counts, list, xil, bad);
 }
 
+void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, int* apos, int* totals,
+                        hipStream_t s) {
+    const int nt = tile_count(g);
+    hipLaunchKernelGGL(k_tile_count, dim3(nt), dim3(TX, TY), 0, s, nbm, g, cnt, base, apos);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, base, nt, totals);      // fluid ids
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, apos, nt, totals + 1);  // active tiles
+}
+
+void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const int* base, const int* apos, int* fid,
+                     uint8_t* loc, int* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_ids, dim3(tile_count(g)), dim3(TX, TY), 0, s, nbm, g, base, cnt, apos, fid, loc,
+                       active);
+}
+
+static unsigned xcd_grid(int nactive) { return (unsigned)(((nactive + 7) / 8) * 8); }
+
 template <class C>
-void launch_init(const Pops<C>& P, const uint32_t* nbm, const float* rho, float2* rprev, const Geo& g,
-                 hipStream_t s) {
-    hipLaunchKernelGGL(k_init<C>, row_grid(g), dim3(64), 0, s, P, nbm, rho, rprev, g);
+void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,
+                 const Geo& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_init<C>, row_grid(g), dim3(64), 0, s, P, nbm, fid, rho, rprev, g);
 }
 
 template <class C>
-void launch_density(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, float2* psi,
+void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
                     const Geo& g, int odd, hipStream_t s) {
-    const TileGrid T = tiles(g);
+    if (S.nactive <= 0) return;
     if (odd)
-        hipLaunchKernelGGL((k_density<C, true>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, T);
+        hipLaunchKernelGGL((k_density<C, true>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, S, nbm,
+                           rprev, psi, g);
     else
-        hipLaunchKernelGGL((k_density<C, false>), dim3(T.grid), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, T);
+        hipLaunchKernelGGL((k_density<C, false>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, S, nbm,
+                           rprev, psi, g);
 }
 
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
@@ -442,15 +526,16 @@ void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* n
 }
 
 template <class C>
-void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const uint32_t* nbm, const float2* rprev,
-                           const float2* psi, const Geo& g, const Phys& ph, int odd, hipStream_t s) {
-    const TileGrid T = tiles(g);
+void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
+                           const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, int odd,
+                           hipStream_t s) {
+    if (S.nactive <= 0) return;
     if (odd)
-        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(T.grid), dim3(TX, TY), 0, s, P, D, nbm, rprev,
-                           psi, g, ph, T);
+        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, D, S,
+                           nbm, rprev, psi, g, ph);
     else
-        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(T.grid), dim3(TX, TY), 0, s, P, D, nbm, rprev,
-                           psi, g, ph, T);
+        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, D,
+                           S, nbm, rprev, psi, g, ph);
 }
 
 int fields_blocks(const Geo& g) {
@@ -459,31 +544,31 @@ int fields_blocks(const Geo& g) {
 }
 
 template <class C>
-void launch_fields(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,
-                   const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F,
-                   float* o_P, double* partial, double* out, hipStream_t s) {
+void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, const float2* psi,
+                   const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F, float* o_P,
+                   double* partial, double* out, hipStream_t s) {
     if (odd)
-        hipLaunchKernelGGL((k_fields<C, true>), tile_grid3(g), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, ph,
-                           o_rho, o_u, o_F, o_P, partial);
+        hipLaunchKernelGGL((k_fields<C, true>), tile_grid3(g), dim3(TX, TY), 0, s, P, fid, nbm, rprev, psi, g,
+                           ph, o_rho, o_u, o_F, o_P, partial);
     else
-        hipLaunchKernelGGL((k_fields<C, false>), tile_grid3(g), dim3(TX, TY), 0, s, P, nbm, rprev, psi, g, ph,
-                           o_rho, o_u, o_F, o_P, partial);
+        hipLaunchKernelGGL((k_fields<C, false>), tile_grid3(g), dim3(TX, TY), 0, s, P, fid, nbm, rprev, psi, g,
+                           ph, o_rho, o_u, o_F, o_P, partial);
     if (partial)
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, (const double*)partial,
                            fields_blocks(g), out);
 }
 
-#define MCLBM_INSTANTIATE(C)                                                                           \
-    template void launch_init<C>(const Pops<C>&, const uint32_t*, const float*, float2*, const Geo&,   \
-                                 hipStream_t);                                                         \
-    template void launch_density<C>(const Pops<C>&, const uint32_t*, const float2*, float2*,           \
-                                    const Geo&, int, hipStream_t);                                     \
-    template void launch_collide_stream<C>(const Pops<C>&, const Pops<C>&, const uint32_t*,            \
-                                           const float2*, const float2*, const Geo&, const Phys&, int, \
-                                           hipStream_t);                                               \
-    template void launch_fields<C>(const Pops<C>&, const uint32_t*, const float2*, const float2*,      \
-                                   const Geo&, const Phys&, int, float*, float*, float*, float*,       \
-                                   double*, double*, hipStream_t);
+#define MCLBM_INSTANTIATE(C)                                                                              \
+    template void launch_init<C>(const Pops<C>&, const uint32_t*, const int*, const float*, float2*,      \
+                                 const Geo&, hipStream_t);                                                \
+    template void launch_density<C>(const Pops<C>&, const Sparse&, const uint32_t*, const float2*,        \
+                                    float2*, const Geo&, int, hipStream_t);                               \
+    template void launch_collide_stream<C>(const Pops<C>&, const Pops<C>&, const Sparse&, const uint32_t*, \
+                                           const float2*, const float2*, const Geo&, const Phys&, int,    \
+                                           hipStream_t);                                                  \
+    template void launch_fields<C>(const Pops<C>&, const int*, const uint32_t*, const float2*,            \
+                                   const float2*, const Geo&, const Phys&, int, float*, float*, float*,   \
+                                   float*, double*, double*, hipStream_t);
 
 MCLBM_INSTANTIATE(CodecF32)
 MCLBM_INSTANTIATE(CodecF16)

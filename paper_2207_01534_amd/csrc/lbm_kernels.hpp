@@ -5,27 +5,47 @@
 
 namespace mclbm {
 
+// Tile-sparse index structures (built once per geometry).
+struct Sparse {
+    const int* active;   // ids of the tiles that hold fluid, in tile order
+    const int* base;     // per tile: fluid id of its first fluid node
+    const int* count;    // per tile: number of fluid nodes
+    const uint8_t* loc;  // per fluid node: position inside its tile (x + 64 y)
+    const int* fid;      // per lattice node: fluid id, -1 at solid
+    int nactive;
+};
+
 void launch_store_words(uint64_t* dst, const uint64_t (&w)[4], hipStream_t s);
 void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hipStream_t s);
 int boundary_blocks(const Geo& g);
 void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int* total, int* list,
                           float* xil, int* bad, const Geo& g, hipStream_t s);
+int tile_count(const Geo& g);
+// Per-tile fluid counts and their scans: totals[0] <- number of fluid nodes,
+// totals[1] <- number of tiles holding fluid.
+void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, int* apos, int* totals,
+                        hipStream_t s);
+// Fluid ids, in-tile positions and the active tile list; loc must hold
+// totals[0] entries.
+void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const int* base, const int* apos, int* fid,
+                     uint8_t* loc, int* active, hipStream_t s);
 
 template <class C>
-void launch_init(const Pops<C>& P, const uint32_t* nbm, const float* rho, float2* rprev, const Geo& g,
-                 hipStream_t s);
+void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,
+                 const Geo& g, hipStream_t s);
 template <class C>
-void launch_density(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, float2* psi,
+void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
                     const Geo& g, int odd, hipStream_t s);
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
                  const Geo& g, hipStream_t s);
 template <class C>
-void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const uint32_t* nbm, const float2* rprev,
-                           const float2* psi, const Geo& g, const Phys& ph, int odd, hipStream_t s);
+void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
+                           const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, int odd,
+                           hipStream_t s);
 int fields_blocks(const Geo& g);
 template <class C>
-void launch_fields(const Pops<C>& P, const uint32_t* nbm, const float2* rprev, const float2* psi,
-                   const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F,
-                   float* o_P, double* partial, double* out, hipStream_t s);
+void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, const float2* psi,
+                   const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F, float* o_P,
+                   double* partial, double* out, hipStream_t s);
 
 }  // namespace mclbm

@@ -38,17 +38,26 @@ size_t elem_bytes(int storage) { return storage == MCLBM_F32 ? 4 : 2; }
 
 struct Layout {
     size_t mv, rest, R0, R1, nbm, list, xil, counts, bad, partial, misc, total;
+    size_t fid, loc, tcnt, tbase, tapos, tact;
     size_t mv_bytes, rest_bytes, r_bytes;
-    int np;
+    int np, cap;
 };
+
+int capacity_of(const mclbm_params& p) {
+    const int n = p.nx * p.ny * p.nz;
+    return p.fluid_capacity > 0 && p.fluid_capacity < n ? p.fluid_capacity : n;
+}
 
 Layout make_layout(const mclbm_params& p) {
     Layout L{};
     const size_t n = (size_t)p.nx * p.ny * p.nz;
-    // plane stride: padded and skewed by 256 elements so that the 38 streams
-    // do not start on the same HBM channel when n is a power of two
-    L.np = (int)align_up(n + 256, 256);
+    L.cap = capacity_of(p);
+    // population planes hold the fluid nodes only; the stride is padded and
+    // skewed by 256 elements so that the 38 streams do not start on the same
+    // HBM channel when the capacity is a power of two
+    L.np = (int)align_up((size_t)L.cap + 256, 256);
     const Geo g{p.nx, p.ny, p.nz, (int)n, L.np};
+    const size_t nt = (size_t)tile_count(g);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -68,6 +77,12 @@ Layout make_layout(const mclbm_params& p) {
     L.counts = take((size_t)boundary_blocks(g) * sizeof(int));
     L.bad = take((size_t)boundary_blocks(g) * sizeof(int));
     L.partial = take((size_t)fields_blocks(g) * 8 * sizeof(double));
+    L.fid = take(n * sizeof(int));
+    L.loc = take((size_t)L.cap);
+    L.tcnt = take(nt * sizeof(int));
+    L.tbase = take(nt * sizeof(int));
+    L.tapos = take(nt * sizeof(int));
+    L.tact = take(nt * sizeof(int));
     L.misc = take(256);
     L.total = off;
     return L;
@@ -80,7 +95,7 @@ mclbm_status check_params(const mclbm_params* p) {
     const double n = (double)p->nx * p->ny * p->nz;
     if (n + 512 >= 1073741824.0) return fail(MCLBM_EINVAL, "nx*ny*nz must be < 2^30");
     if (p->storage < MCLBM_F32 || p->storage > MCLBM_BF16) return fail(MCLBM_EINVAL, "bad storage");
-    if (p->reserved != 0) return fail(MCLBM_EINVAL, "reserved must be 0");
+    if (p->fluid_capacity < 0) return fail(MCLBM_EINVAL, "fluid_capacity must be >= 0");
     for (int s = 0; s < 2; ++s) {
         if (!(p->tau[s] > 0.5) || !std::isfinite(p->tau[s]))
             return fail(MCLBM_EINVAL, "tau must be finite and > 0.5");
@@ -102,6 +117,8 @@ struct mclbm_lattice {
     char* ws;
     int64_t t;
     int nbound;
+    int nfluid;
+    int nactive;
     bool geometry;
     bool initialized;
     // per-kernel event pairs recorded by mclbm_step while profiling
@@ -115,6 +132,11 @@ struct mclbm_lattice {
     double* partial() const { return (double*)(ws + L.partial); }
     int* misc_int() const { return (int*)(ws + L.misc); }
     double* diag_out() const { return (double*)(ws + L.misc + 64); }
+    int* fid() const { return (int*)(ws + L.fid); }
+    Sparse sparse() const {
+        return Sparse{(const int*)(ws + L.tact), (const int*)(ws + L.tbase), (const int*)(ws + L.tcnt),
+                      (const uint8_t*)(ws + L.loc), fid(), nactive};
+    }
 
     template <class C>
     Pops<C> pops() const {
@@ -136,7 +158,7 @@ struct mclbm_lattice {
         const float2* rprev = R((int)((t + 1) & 1));
         with_codec([&](auto c) {
             using C = decltype(c);
-            launch_density<C>(pops<C>(), nbm(), rprev, psi, g, odd, stream);
+            launch_density<C>(pops<C>(), sparse(), nbm(), rprev, psi, g, odd, stream);
         });
         launch_ivsd(list(), xil(), nbound, nbm(), psi, g, stream);
     }
@@ -147,8 +169,8 @@ struct mclbm_lattice {
         const float2* rprev = R((int)((t + 1) & 1));
         with_codec([&](auto c) {
             using C = decltype(c);
-            launch_fields<C>(pops<C>(), nbm(), rprev, psi, g, ph, odd, o_rho, o_u, o_F, o_P, partial, out,
-                             stream);
+            launch_fields<C>(pops<C>(), fid(), nbm(), rprev, psi, g, ph, odd, o_rho, o_u, o_F, o_P, partial,
+                             out, stream);
         });
     }
 };
@@ -188,6 +210,8 @@ mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t 
     lat->ws = (char*)d_workspace;
     lat->t = 0;
     lat->nbound = 0;
+    lat->nfluid = 0;
+    lat->nactive = 0;
     lat->geometry = false;
     lat->initialized = false;
     *out = lat;
@@ -202,22 +226,40 @@ mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, cons
     int* bad = (int*)(lat->ws + lat->L.bad);
     launch_boundary_list(lat->nbm(), d_xi, counts, lat->misc_int(), lat->list(), lat->xil(), bad, g,
                          lat->stream);
+    const Layout& L = lat->L;
+    int* tcnt = (int*)(lat->ws + L.tcnt);
+    int* tbase = (int*)(lat->ws + L.tbase);
+    int* tapos = (int*)(lat->ws + L.tapos);
+    launch_tile_census(lat->nbm(), g, tcnt, tbase, tapos, lat->misc_int() + 1, lat->stream);
     HIP_TRY(hipGetLastError());
     const int nb = boundary_blocks(g);
     std::vector<int> hbad(nb);
-    int total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, lat->misc_int(), sizeof(int), hipMemcpyDeviceToHost, lat->stream));
+    int totals[3] = {0, 0, 0};  // boundary solids, fluid nodes, active tiles
+    HIP_TRY(hipMemcpyAsync(totals, lat->misc_int(), sizeof(totals), hipMemcpyDeviceToHost, lat->stream));
     HIP_TRY(hipMemcpyAsync(hbad.data(), bad, nb * sizeof(int), hipMemcpyDeviceToHost, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->geometry = false;
+    lat->initialized = false;
     for (int b = 0; b < nb; ++b)
-        if (hbad[b]) {
-            lat->geometry = false;
-            return fail(MCLBM_EINVAL, "|xi| must be < 1 at solid voxels with a fluid neighbour");
-        }
-    lat->nbound = total;
+        if (hbad[b]) return fail(MCLBM_EINVAL, "|xi| must be < 1 at solid voxels with a fluid neighbour");
+    if (totals[1] > L.cap) return fail(MCLBM_EINVAL, "more fluid voxels than params.fluid_capacity");
+    // fluid ids are assigned only once they are known to fit the capacity
+    launch_tile_ids(lat->nbm(), g, tcnt, tbase, tapos, lat->fid(), (uint8_t*)(lat->ws + L.loc),
+                    (int*)(lat->ws + L.tact), lat->stream);
+    HIP_TRY(hipGetLastError());
+    lat->nbound = totals[0];
+    lat->nfluid = totals[1];
+    lat->nactive = totals[2];
     lat->geometry = true;
     lat->initialized = false;
     lat->t = 0;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_fluid_count(const mclbm_lattice* lat, int64_t* count) {
+    if (!lat || !count) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->geometry) return fail(MCLBM_ESTATE, "geometry not set");
+    *count = lat->nfluid;
     return MCLBM_OK;
 }
 
@@ -234,7 +276,7 @@ mclbm_status mclbm_init_equilibrium(mclbm_lattice* lat, const float* d_rho) {
     // state at t = 0; the codecs' reference density of the previous level is R[1]
     lat->with_codec([&](auto c) {
         using C = decltype(c);
-        launch_init<C>(lat->pops<C>(), lat->nbm(), d_rho, lat->R(1), lat->g, lat->stream);
+        launch_init<C>(lat->pops<C>(), lat->nbm(), lat->fid(), d_rho, lat->R(1), lat->g, lat->stream);
     });
     HIP_TRY(hipGetLastError());
     lat->t = 0;
@@ -261,14 +303,14 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
         lat->with_codec([&](auto c) {
             using C = decltype(c);
             mark(0);
-            launch_density<C>(lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, odd, lat->stream);
+            launch_density<C>(lat->pops<C>(), lat->sparse(), lat->nbm(), rprev, psi, lat->g, odd, lat->stream);
             mark(0);
             mark(1);
             launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, lat->g, lat->stream);
             mark(1);
             mark(2);
-            launch_collide_stream<C>(lat->pops<C>(), lat->pops<C>(), lat->nbm(), rprev, psi, lat->g, lat->ph, odd,
-                                     lat->stream);
+            launch_collide_stream<C>(lat->pops<C>(), lat->pops<C>(), lat->sparse(), lat->nbm(), rprev, psi, lat->g,
+                                     lat->ph, odd, lat->stream);
             mark(2);
         });
         lat->t += 1;
@@ -396,7 +438,7 @@ mclbm_status mclbm_loss_snw(mclbm_lattice* lat, const uint8_t* d_region, double*
     if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
     if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
     double out[2];
-    launch_loss(lat->pops<CodecF32>(), lat->nbm(), d_region, lat->g, (int)(lat->t & 1), lat->partial(),
+    launch_loss(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, lat->g, (int)(lat->t & 1), lat->partial(),
                 lat->diag_out(), lat->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(out, lat->diag_out(), sizeof(out), hipMemcpyDeviceToHost, lat->stream));
@@ -495,11 +537,11 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
     launch_zero(W.gacc, (size_t)lat->nbound * sizeof(double), s);
     launch_zero(d_grad_xi, n * sizeof(double), s);
     // seed from the final state (the lattice's current populations)
-    launch_loss(lat->pops<CodecF32>(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->partial(), lat->diag_out(),
-                s);
+    launch_loss(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->partial(),
+                lat->diag_out(), s);
     int cur = 0;  // lam[cur], rbar[cur] hold dL/df at the time level being processed
-    launch_adj_seed(lat->pops<CodecF32>(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->diag_out(), W.lam[cur],
-                    W.rbar[cur], s);
+    launch_adj_seed(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->diag_out(),
+                    W.lam[cur], W.rbar[cur], s);
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int64_t ta = t0 + (int64_t)seg * every;
         const int len = (int)((ta + every <= t_end ? ta + every : t_end) - ta);
@@ -512,11 +554,12 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
             const int odd = (int)((ta + k) & 1);
             const Pops<CodecF32> sk = slot_pops(W.seg + (size_t)k * slot, L);
             float2* psi = (float2*)(W.psi + (size_t)k * psi_stride);
-            launch_density<CodecF32>(sk, lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g, odd, s);
+            launch_density<CodecF32>(sk, lat->sparse(), lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g, odd,
+                                     s);
             launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, g, s);
             if (k + 1 < len) {
                 const Pops<CodecF32> sn = slot_pops(W.seg + (size_t)(k + 1) * slot, L);
-                launch_collide_stream<CodecF32>(sk, sn, lat->nbm(), psi, psi, g, lat->ph, odd, s);
+                launch_collide_stream<CodecF32>(sk, sn, lat->sparse(), lat->nbm(), psi, psi, g, lat->ph, odd, s);
             }
         }
         // reverse steps
@@ -525,7 +568,8 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
             const Pops<CodecF32> sk = slot_pops(W.seg + (size_t)k * slot, L);
             const float2* psi = (const float2*)(W.psi + (size_t)k * psi_stride);
             const int nxt = cur, now = 1 - cur;
-            launch_adj_collide(sk, lat->nbm(), psi, W.lam[nxt], W.rbar[nxt], W.lam[now], W.abar, g, lat->ph, odd, s);
+            launch_adj_collide(sk, lat->fid(), lat->nbm(), psi, W.lam[nxt], W.rbar[nxt], W.lam[now], W.abar, g,
+                               lat->ph, odd, s);
             launch_adj_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, W.abar, g, W.gacc, W.nbar, s);
             launch_adj_rho(lat->nbm(), W.abar, W.nbar, g, W.rbar[now], s);
             cur = now;

@@ -34,7 +34,7 @@ class _Params(ctypes.Structure):
     _fields_ = [
         ("abi_version", ctypes.c_uint32),
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("fluid_capacity", ctypes.c_int32),
         ("tau", ctypes.c_double * 2),
         ("G", ctypes.c_double),
         ("g", (ctypes.c_double * 3) * 2),
@@ -52,6 +52,7 @@ SIGNATURES = [
     ("mclbm_workspace_bytes", _I32, [_PP, _SZP]),
     ("mclbm_create", _I32, [_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     ("mclbm_set_geometry", _I32, [_VP, _VP, _VP]),
+    ("mclbm_fluid_count", _I32, [_VP, _I64P]),
     ("mclbm_boundary_count", _I32, [_VP, _I64P]),
     ("mclbm_init_equilibrium", _I32, [_VP, _VP]),
     ("mclbm_step", _I32, [_VP, _I32]),
@@ -108,13 +109,14 @@ class LatticeParams:
     G: float = 3.5
     g: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
     storage: Storage = Storage.F32
+    fluid_capacity: int = 0                    # fluid voxels the workspace holds (0 = all nodes)
 
     def c(self):
         p = _Params()
         p.abi_version = ABI_VERSION
         p.nx, p.ny, p.nz = (int(v) for v in self.shape)
         p.storage = int(self.storage)
-        p.reserved = 0
+        p.fluid_capacity = int(self.fluid_capacity)
         p.tau[0], p.tau[1] = (float(v) for v in self.tau)
         p.G = float(self.G)
         for s in range(2):
@@ -171,6 +173,11 @@ class Lattice:
         xi_t = _dev_tensor(xi, torch.float32, self.device).reshape(self.dims)
         with torch.cuda.stream(self.stream):
             _check(_lib.mclbm_set_geometry(self._h, _ptr(solid_t), _ptr(xi_t)), "set_geometry")
+
+    def fluid_count(self) -> int:
+        c = ctypes.c_int64()
+        _check(_lib.mclbm_fluid_count(self._h, ctypes.byref(c)), "fluid_count")
+        return c.value
 
     def boundary_count(self) -> int:
         c = ctypes.c_int64()

@@ -69,6 +69,14 @@ def test_invalid_parameters_rejected(lib, kw, code):
     assert lib.mclbm_last_error()
 
 
+def test_fluid_capacity_shrinks_population_storage(lib):
+    _, full = _bytes(lib, shape=(64, 64, 64))
+    _, part = _bytes(lib, shape=(64, 64, 64), fluid_capacity=64 * 64 * 16)
+    assert full - part >= 38 * 4 * 64 * 64 * 48
+    st, _ = _bytes(lib, shape=(8, 8, 8), fluid_capacity=-1)
+    assert st == -1
+
+
 def test_version_mismatch_rejected(lib):
     p = L.LatticeParams(shape=(8, 8, 8)).c()
     p.abi_version = 99
