@@ -1,8 +1,8 @@
 // HIP kernels of the two-component D3Q19 pseudopotential step (gfx950).
 //
 // Populations are stored only for fluid nodes, compacted within tiles of
-// 64 x 4 nodes of one z plane; tiles without fluid are dropped (the paper's
-// sparse tiling, Sec. 5, with node compaction inside each tile).  One time
+// 64 x 4 x 2 nodes; tiles without fluid are dropped (the paper's sparse
+// tiling, Sec. 5, with node compaction inside each tile).  One time
 // step is three launches on the caller's stream:
 //   k_density        rho^(sigma) at every fluid node from the incoming
 //                    populations (Eq. 3), written to the dense psi-hat field.
@@ -81,13 +81,13 @@ __global__ void k_scan(int* __restrict__ counts, int nblocks, int* __restrict__ 
 // (ordered by linear thread id); the block's flagged count goes to *count.
 __device__ __forceinline__ int block_rank(bool flag, int* wave_off, int* count) {
     const unsigned long long ball = __ballot(flag);
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int tid = (threadIdx.z * blockDim.y + threadIdx.y) * blockDim.x + threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int rank = __popcll(ball & ((1ull << lane) - 1ull));
     if (lane == 0) wave_off[wave] = __popcll(ball);
     __syncthreads();
     int base = 0, all = 0;
-    const int nw = (int)(blockDim.x * blockDim.y) >> 6;
+    const int nw = (int)(blockDim.x * blockDim.y * blockDim.z) >> 6;
     for (int w = 0; w < nw; ++w) {
         if (w < wave) base += wave_off[w];
         all += wave_off[w];
@@ -117,28 +117,31 @@ __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* 
 }
 
 // ---------------------------------------------------------------------------
-// Tiles: 64 x 4 nodes of one z plane, numbered x fastest, then y, then z.
+// Tiles: 64 x 4 x 2 nodes, numbered x fastest, then y, then z.  A tile's
+// fluid nodes are handled by 256 threads, two nodes per thread at most.
 // ---------------------------------------------------------------------------
-constexpr int TX = 64, TY = 4;
-constexpr int HX = TX + 2, HY = TY + 2;
+constexpr int TX = 64, TY = 4, TZ = 2;
+constexpr int TN = TX * TY * TZ;   // nodes per tile
+constexpr int NT = 256;            // threads per block of the tile kernels
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 
-__device__ __forceinline__ void tile_origin(int t, const Geo& g, int& x0, int& y0, int& z) {
+__device__ __forceinline__ void tile_origin(int t, const Geo& g, int& x0, int& y0, int& z0) {
     const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
     x0 = (t % ntx) * TX;
     y0 = ((t / ntx) % nty) * TY;
-    z = t / (ntx * nty);
+    z0 = (t / (ntx * nty)) * TZ;
 }
 
 // Per tile: number of fluid nodes (into cnt and, for the scans, into base
-// and active_flag).
+// and active_flag).  Block = (64, 4, 2), one thread per tile node.
 __global__ void k_tile_count(const uint32_t* __restrict__ nbm, Geo g, int* __restrict__ cnt,
                              int* __restrict__ base, int* __restrict__ active_flag) {
-    int x0, y0, z;
-    tile_origin(blockIdx.x, g, x0, y0, z);
-    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-    const bool fluid = x < g.nx && y < g.ny && !(nbm[x + g.nx * (y + g.ny * z)] & SELF_SOLID);
+    int x0, y0, z0;
+    tile_origin(blockIdx.x, g, x0, y0, z0);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y, z = z0 + threadIdx.z;
+    const bool fluid = x < g.nx && y < g.ny && z < g.nz && !(nbm[x + g.nx * (y + g.ny * z)] & SELF_SOLID);
     const int c = __syncthreads_count(fluid);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
+    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) {
         cnt[blockIdx.x] = c;
         base[blockIdx.x] = c;
         active_flag[blockIdx.x] = c > 0 ? 1 : 0;
@@ -149,19 +152,20 @@ __global__ void k_tile_count(const uint32_t* __restrict__ nbm, Geo g, int* __res
 // (-1 at solid) and each fluid node's position inside its tile.
 __global__ void k_tile_ids(const uint32_t* __restrict__ nbm, Geo g, const int* __restrict__ base,
                            const int* __restrict__ cnt, const int* __restrict__ active_pos,
-                           int* __restrict__ fid, uint8_t* __restrict__ loc, int* __restrict__ active) {
-    __shared__ int wave_off[TX * TY / 64];
-    int x0, y0, z;
-    tile_origin(blockIdx.x, g, x0, y0, z);
-    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-    const bool inside = x < g.nx && y < g.ny;
+                           int* __restrict__ fid, uint16_t* __restrict__ loc, int* __restrict__ active) {
+    __shared__ int wave_off[TN / 64];
+    int x0, y0, z0;
+    tile_origin(blockIdx.x, g, x0, y0, z0);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y, z = z0 + threadIdx.z;
+    const bool inside = x < g.nx && y < g.ny && z < g.nz;
     const int idx = x + g.nx * (y + g.ny * z);
     const bool fluid = inside && !(nbm[idx] & SELF_SOLID);
     int c;
     const int rank = block_rank(fluid, wave_off, &c);
     if (inside) fid[idx] = fluid ? base[blockIdx.x] + rank : -1;
-    if (fluid) loc[base[blockIdx.x] + rank] = (uint8_t)(threadIdx.x + TX * threadIdx.y);
-    if (threadIdx.x == 0 && threadIdx.y == 0 && cnt[blockIdx.x] > 0) active[active_pos[blockIdx.x]] = blockIdx.x;
+    if (fluid) loc[base[blockIdx.x] + rank] = (uint16_t)(threadIdx.x + TX * (threadIdx.y + TY * threadIdx.z));
+    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0 && cnt[blockIdx.x] > 0)
+        active[active_pos[blockIdx.x]] = blockIdx.x;
 }
 
 // ---------------------------------------------------------------------------
@@ -216,12 +220,12 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* _
 }
 
 // ---------------------------------------------------------------------------
-// Tile kernels.  One block of 256 threads per active tile; thread j < count
-// handles the tile's j-th fluid node.  Blocks are numbered on a 1D grid and
-// mapped XCD-aware: the hardware deals consecutive block ids round-robin to
-// the 8 XCDs, so block b takes active tile (b mod 8) * per + b / 8 and each
-// XCD works through a contiguous run of neighbouring tiles, whose shared
-// halo rows then hit in that XCD's L2.
+// Tile kernels.  One block of 256 threads per active tile; thread j handles
+// the tile's fluid nodes j and j + 256 (when they exist).  Blocks are
+// numbered on a 1D grid and mapped XCD-aware: the hardware deals
+// consecutive block ids round-robin to the 8 XCDs, so block b takes active
+// tile (b mod 8) * per + b / 8 and each XCD works through a contiguous run
+// of neighbouring tiles, whose shared halo rows then hit in that XCD's L2.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int active_of_block(int nactive) {
     const int per = gridDim.x >> 3;
@@ -229,13 +233,15 @@ __device__ __forceinline__ int active_of_block(int nactive) {
     return a < nactive ? a : -1;
 }
 
-// Stage values of planes z-1, z, z+1 over the tile plus a one-node halo.
+// Stage values of planes z0-1 .. z0+2 over the tile plus a one-node halo.
 template <class T, class Src>
-__device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, int z, const Geo& g, Src src,
+__device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, int z0, const Geo& g, Src src,
                                            T fill) {
     const int nxy = g.nx * g.ny;
-    const int zs[3] = {(z == 0 ? g.nz - 1 : z - 1) * nxy, z * nxy, (z == g.nz - 1 ? 0 : z + 1) * nxy};
-    for (int k = threadIdx.x; k < 3 * HX * HY; k += TX * TY) {
+    int zs[HZ];
+#pragma unroll
+    for (int p = 0; p < HZ; ++p) zs[p] = ((z0 - 1 + p + g.nz) % g.nz) * nxy;
+    for (int k = threadIdx.x; k < HZ * HX * HY; k += NT) {
         const int pl = k / (HX * HY);
         const int r = k - pl * (HX * HY);
         const int hy = r / HX, hx = r - hy * HX;
@@ -248,33 +254,41 @@ __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, in
     }
 }
 
+// Position of a fluid node inside its tile.
+struct TilePos {
+    int lx, ly, lz;
+    __device__ __forceinline__ explicit TilePos(int p) : lx(p & (TX - 1)), ly((p / TX) & (TY - 1)), lz(p / (TX * TY)) {}
+};
+
 // K1: densities.  psi[x] = (rho1, rho2) at fluid nodes.
+// 8 waves per SIMD (the density pass needs about 50 VGPRs).
 template <class C, bool ODD>
-__global__ __launch_bounds__(TX * TY) void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm,
-                                                     const float2* __restrict__ rprev,
-                                                     float2* __restrict__ psi, Geo g) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm,
+                                                const float2* __restrict__ rprev, float2* __restrict__ psi,
+                                                Geo g) {
     const int a = active_of_block(S.nactive);
     if (a < 0) return;
     const int t = S.active[a];
-    int x0, y0, z;
-    tile_origin(t, g, x0, y0, z);
+    int x0, y0, z0;
+    tile_origin(t, g, x0, y0, z0);
     const int base = S.base[t], count = S.count[t];
-    __shared__ int fidt[ODD ? 3 : 1][HY][HX];
+    __shared__ int fidt[ODD ? HZ : 1][HY][HX];
     if constexpr (ODD) {
-        stage_halo(fidt, x0, y0, z, g, [&](uint32_t i) { return S.fid[i]; }, -1);
+        stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
         __syncthreads();
     }
-    const int j = threadIdx.x;
-    if (j >= count) return;
-    const uint32_t k = (uint32_t)(base + j);
-    const int p = S.loc[k];
-    const int lx = p & (TX - 1), ly = p / TX;
-    const Nb nb(x0 + lx, y0 + ly, z, g);
-    const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
-    float f[2][Q];
-    auto fid_at = [&](int i, int s) { return fidt[1 + s * DZ[i]][1 + ly + s * DY[i]][1 + lx + s * DX[i]]; };
-    load_node<C, ODD>(f, P, rprev, m, nb, k, fid_at, g.np);
-    st(psi, nb.idx, make_float2(sum19(f[0]), sum19(f[1])));
+    for (int j = threadIdx.x; j < count; j += NT) {
+        const uint32_t k = (uint32_t)(base + j);
+        const TilePos q(S.loc[k]);
+        const Nb nb(x0 + q.lx, y0 + q.ly, z0 + q.lz, g);
+        const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
+        float f[2][Q];
+        auto fid_at = [&](int i, int s) {
+            return fidt[1 + q.lz + s * DZ[i]][1 + q.ly + s * DY[i]][1 + q.lx + s * DX[i]];
+        };
+        load_node<C, ODD>(f, P, rprev, m, nb, k, fid_at, g.np);
+        st(psi, nb.idx, make_float2(sum19(f[0]), sum19(f[1])));
+    }
 }
 
 // K1b: IVSD virtual solid density at boundary solid nodes (Eqs. 14-15):
@@ -306,48 +320,77 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
     psi[idx] = make_float2((1.0f + v) * n0 * inv, (1.0f - v) * n1 * inv);
 }
 
+// Fluid ids of the staged halo around one tile node: fid of x + s e_i, -1
+// at solid nodes.
+struct HaloFid {
+    const int (*t)[HY][HX];
+    int tx, ty, tz;
+    __device__ __forceinline__ int operator()(int i, int s) const {
+        return t[tz + s * DZ[i]][ty + s * DY[i]][tx + s * DX[i]];
+    }
+};
+
 // K2: fused force + collision + streaming for the fluid nodes of one tile.
-// The psi-hat values (and, in odd steps, the fluid ids) of planes z-1, z,
-// z+1 over the tile and a one-node halo are staged in LDS behind one
-// barrier; each node then reads its 18 neighbours from LDS.  P is the state
-// read, D the state written: the same buffer for the in-place step, two
-// buffers when a step is recomputed into a separate slot.
+// The psi-hat values (and, in odd steps, the fluid ids) of planes z0-1 ..
+// z0+2 over the tile and a one-node halo are staged in LDS; each node then
+// reads its 18 neighbours from LDS.  The populations of a thread's first
+// node are requested before the psi-hat staging so that the two overlap:
+// in even steps straight away (they sit in the node's own slots), in odd
+// steps right after the fluid-id halo is in LDS (they are gathered from the
+// neighbours' slots).  P is the state read, D the state written: the same
+// buffer for the in-place step, two buffers when a step is recomputed into
+// a separate slot.
+// Register budgets: the compiler's default schedule holds up to ~140 VGPRs
+// (3 waves per SIMD), too few waves to hide the memory latency of the
+// population traffic.  Even steps fit 5 waves per SIMD without spilling; odd
+// steps (gathers through the fluid-id halo) are held to 4.
 template <class C, bool ODD>
-__global__ __launch_bounds__(TX * TY) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
-                                                            const uint32_t* __restrict__ nbm,
-                                                            const float2* __restrict__ rprev,
-                                                            const float2* __restrict__ psi, Geo g, Phys ph) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 5))) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
+                                                       const uint32_t* __restrict__ nbm,
+                                                       const float2* __restrict__ rprev,
+                                                       const float2* __restrict__ psi, Geo g, Phys ph) {
     const int a = active_of_block(S.nactive);
     if (a < 0) return;
     const int t = S.active[a];
-    int x0, y0, z;
-    tile_origin(t, g, x0, y0, z);
+    int x0, y0, z0;
+    tile_origin(t, g, x0, y0, z0);
     const int base = S.base[t], count = S.count[t];
-    __shared__ float2 psit[3][HY][HX];
-    __shared__ int fidt[ODD ? 3 : 1][HY][HX];
-    stage_halo(psit, x0, y0, z, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
-    if constexpr (ODD) stage_halo(fidt, x0, y0, z, g, [&](uint32_t i) { return S.fid[i]; }, -1);
-    __syncthreads();
-    const int j = threadIdx.x;
-    if (j >= count) return;
-    const uint32_t k = (uint32_t)(base + j);
-    const int p = S.loc[k];
-    const int lx = p & (TX - 1), ly = p / TX;
-    const Nb nb(x0 + lx, y0 + ly, z, g);
-    const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
-    auto fid_at = [&](int i, int s) { return fidt[1 + s * DZ[i]][1 + ly + s * DY[i]][1 + lx + s * DX[i]]; };
-
+    __shared__ float2 psit[HZ][HY][HX];
+    __shared__ int fidt[ODD ? HZ : 1][HY][HX];
+    if constexpr (ODD) {
+        stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
+        __syncthreads();
+    }
+    auto fetch = [&](int j, float (&f)[2][Q], HaloFid& h) {
+        const uint32_t k = (uint32_t)(base + j);
+        const TilePos q(S.loc[k]);
+        h = HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1};
+        const Nb nb(x0 + q.lx, y0 + q.ly, z0 + q.lz, g);
+        const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
+        load_node<C, ODD>(f, P, rprev, m, nb, k, h, g.np);
+    };
+    auto finish = [&](int j, float (&f)[2][Q], const HaloFid& h) {
+        const uint32_t k = (uint32_t)(base + j);
+        const float rho[2] = {sum19(f[0]), sum19(f[1])};
+        float acc[2][3];
+        psi_sum([&](int i) { return psit[h.tz + DZ[i]][h.ty + DY[i]][h.tx + DX[i]]; }, acc);
+        float F[2][3];
+        total_force(rho, acc, ph, F);
+        float u[3];
+        collide(f, rho, F, ph, u);
+        store_node<C, ODD>(f, D, rho, psit[h.tz][h.ty][h.tx], k, h, g.np);
+    };
+    const int j0 = threadIdx.x;
     float f[2][Q];
-    load_node<C, ODD>(f, P, rprev, m, nb, k, fid_at, g.np);
-    const float rho[2] = {sum19(f[0]), sum19(f[1])};
-    const int tx = lx + 1, ty = ly + 1;
-    float acc[2][3];
-    psi_sum([&](int i) { return psit[1 + DZ[i]][ty + DY[i]][tx + DX[i]]; }, acc);
-    float F[2][3];
-    total_force(rho, acc, ph, F);
-    float u[3];
-    collide(f, rho, F, ph, u);
-    store_node<C, ODD>(f, D, rho, psit[1][ty][tx], k, fid_at, g.np);
+    HaloFid h;
+    if (j0 < count) fetch(j0, f, h);
+    stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
+    __syncthreads();
+    if (j0 < count) finish(j0, f, h);
+    for (int j = j0 + NT; j < count; j += NT) {
+        fetch(j, f, h);
+        finish(j, f, h);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -355,7 +398,7 @@ __global__ __launch_bounds__(TX * TY) void k_collide_stream(Pops<C> P, Pops<C> D
 // k_density + k_ivsd for this level).  Dense over all nodes.
 // ---------------------------------------------------------------------------
 template <class C, bool ODD>
-__global__ __launch_bounds__(TX * TY) void k_fields(Pops<C> P, const int* __restrict__ fid,
+__global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict__ fid,
                                                     const uint32_t* __restrict__ nbm,
                                                     const float2* __restrict__ rprev,
                                                     const float2* __restrict__ psi, Geo g, Phys ph,
@@ -465,9 +508,12 @@ void launch_store_words(uint64_t* dst, const uint64_t (&w)[4], hipStream_t s) {
 }
 
 static dim3 row_grid(const Geo& g) { return dim3((g.nx + 63) / 64, g.ny, g.nz); }
-static dim3 tile_grid3(const Geo& g) { return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz); }
+// readout blocks: 64 x 4 nodes of one z plane
+static dim3 tile_grid3(const Geo& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
 
-int tile_count(const Geo& g) { return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * g.nz; }
+int tile_count(const Geo& g) {
+    return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+}
 
 void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hipStream_t s) {
     hipLaunchKernelGGL(k_neighbour_bits, row_grid(g), dim3(64), 0, s, solid, nbm, g);
@@ -487,14 +533,14 @@ void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int
 void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, int* apos, int* totals,
                         hipStream_t s) {
     const int nt = tile_count(g);
-    hipLaunchKernelGGL(k_tile_count, dim3(nt), dim3(TX, TY), 0, s, nbm, g, cnt, base, apos);
+    hipLaunchKernelGGL(k_tile_count, dim3(nt), dim3(TX, TY, TZ), 0, s, nbm, g, cnt, base, apos);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, base, nt, totals);      // fluid ids
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, apos, nt, totals + 1);  // active tiles
 }
 
 void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const int* base, const int* apos, int* fid,
-                     uint8_t* loc, int* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_ids, dim3(tile_count(g)), dim3(TX, TY), 0, s, nbm, g, base, cnt, apos, fid, loc,
+                     uint16_t* loc, int* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_ids, dim3(tile_count(g)), dim3(TX, TY, TZ), 0, s, nbm, g, base, cnt, apos, fid, loc,
                        active);
 }
 
@@ -511,11 +557,11 @@ void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, cons
                     const Geo& g, int odd, hipStream_t s) {
     if (S.nactive <= 0) return;
     if (odd)
-        hipLaunchKernelGGL((k_density<C, true>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, S, nbm,
-                           rprev, psi, g);
+        hipLaunchKernelGGL((k_density<C, true>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, nbm, rprev,
+                           psi, g);
     else
-        hipLaunchKernelGGL((k_density<C, false>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, S, nbm,
-                           rprev, psi, g);
+        hipLaunchKernelGGL((k_density<C, false>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, nbm, rprev,
+                           psi, g);
 }
 
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
@@ -531,11 +577,11 @@ void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, 
                            hipStream_t s) {
     if (S.nactive <= 0) return;
     if (odd)
-        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, D, S,
-                           nbm, rprev, psi, g, ph);
+        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, nbm,
+                           rprev, psi, g, ph);
     else
-        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(xcd_grid(S.nactive)), dim3(TX * TY), 0, s, P, D,
-                           S, nbm, rprev, psi, g, ph);
+        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, nbm,
+                           rprev, psi, g, ph);
 }
 
 int fields_blocks(const Geo& g) {
@@ -548,10 +594,10 @@ void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const 
                    const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F, float* o_P,
                    double* partial, double* out, hipStream_t s) {
     if (odd)
-        hipLaunchKernelGGL((k_fields<C, true>), tile_grid3(g), dim3(TX, TY), 0, s, P, fid, nbm, rprev, psi, g,
+        hipLaunchKernelGGL((k_fields<C, true>), tile_grid3(g), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
                            ph, o_rho, o_u, o_F, o_P, partial);
     else
-        hipLaunchKernelGGL((k_fields<C, false>), tile_grid3(g), dim3(TX, TY), 0, s, P, fid, nbm, rprev, psi, g,
+        hipLaunchKernelGGL((k_fields<C, false>), tile_grid3(g), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
                            ph, o_rho, o_u, o_F, o_P, partial);
     if (partial)
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, (const double*)partial,

@@ -10,7 +10,7 @@ struct Sparse {
     const int* active;   // ids of the tiles that hold fluid, in tile order
     const int* base;     // per tile: fluid id of its first fluid node
     const int* count;    // per tile: number of fluid nodes
-    const uint8_t* loc;  // per fluid node: position inside its tile (x + 64 y)
+    const uint16_t* loc; // per fluid node: position inside its tile (x + 64 (y + 4 z))
     const int* fid;      // per lattice node: fluid id, -1 at solid
     int nactive;
 };
@@ -28,7 +28,7 @@ void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, 
 // Fluid ids, in-tile positions and the active tile list; loc must hold
 // totals[0] entries.
 void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const int* base, const int* apos, int* fid,
-                     uint8_t* loc, int* active, hipStream_t s);
+                     uint16_t* loc, int* active, hipStream_t s);
 
 template <class C>
 void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,

@@ -78,7 +78,7 @@ Layout make_layout(const mclbm_params& p) {
     L.bad = take((size_t)boundary_blocks(g) * sizeof(int));
     L.partial = take((size_t)fields_blocks(g) * 8 * sizeof(double));
     L.fid = take(n * sizeof(int));
-    L.loc = take((size_t)L.cap);
+    L.loc = take((size_t)L.cap * sizeof(uint16_t));
     L.tcnt = take(nt * sizeof(int));
     L.tbase = take(nt * sizeof(int));
     L.tapos = take(nt * sizeof(int));
@@ -135,7 +135,7 @@ struct mclbm_lattice {
     int* fid() const { return (int*)(ws + L.fid); }
     Sparse sparse() const {
         return Sparse{(const int*)(ws + L.tact), (const int*)(ws + L.tbase), (const int*)(ws + L.tcnt),
-                      (const uint8_t*)(ws + L.loc), fid(), nactive};
+                      (const uint16_t*)(ws + L.loc), fid(), nactive};
     }
 
     template <class C>
@@ -244,7 +244,7 @@ mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, cons
         if (hbad[b]) return fail(MCLBM_EINVAL, "|xi| must be < 1 at solid voxels with a fluid neighbour");
     if (totals[1] > L.cap) return fail(MCLBM_EINVAL, "more fluid voxels than params.fluid_capacity");
     // fluid ids are assigned only once they are known to fit the capacity
-    launch_tile_ids(lat->nbm(), g, tcnt, tbase, tapos, lat->fid(), (uint8_t*)(lat->ws + L.loc),
+    launch_tile_ids(lat->nbm(), g, tcnt, tbase, tapos, lat->fid(), (uint16_t*)(lat->ws + L.loc),
                     (int*)(lat->ws + L.tact), lat->stream);
     HIP_TRY(hipGetLastError());
     lat->nbound = totals[0];
@@ -288,18 +288,19 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
     if (!lat) return fail(MCLBM_EINVAL, "NULL handle");
     if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
     if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    hipError_t mark_err = hipSuccess;  // first failure of the profiling events
+    auto mark = [&](int k) {
+        if (!lat->profiling || mark_err != hipSuccess) return;
+        hipEvent_t e;
+        mark_err = hipEventCreate(&e);
+        if (mark_err != hipSuccess) return;
+        lat->ev[k].push_back(e);
+        mark_err = hipEventRecord(e, lat->stream);
+    };
     for (int32_t k = 0; k < nsteps; ++k) {
         const int odd = (int)(lat->t & 1);
         float2* psi = lat->R((int)(lat->t & 1));
         const float2* rprev = lat->R((int)((lat->t + 1) & 1));
-        auto mark = [&](int k) -> hipError_t {
-            if (!lat->profiling) return hipSuccess;
-            hipEvent_t e;
-            hipError_t err = hipEventCreate(&e);
-            if (err != hipSuccess) return err;
-            lat->ev[k].push_back(e);
-            return hipEventRecord(e, lat->stream);
-        };
         lat->with_codec([&](auto c) {
             using C = decltype(c);
             mark(0);
@@ -316,6 +317,7 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
         lat->t += 1;
     }
     HIP_TRY(hipGetLastError());
+    HIP_TRY(mark_err);
     return MCLBM_OK;
 }
 
