@@ -299,15 +299,19 @@ __global__ __launch_bounds__(256) void k_adj_ivsd(const int* __restrict__ list, 
     const Nb nb(x, y, z, g);
     const uint32_t m = nbm[idx];
     const float2 pb = psi_adjoint(abar, nb, (size_t)g.n);
+    // all neighbour loads issued together (psi is read-only here); solid
+    // neighbours are dropped by a select
+    float2 r[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) r[i] = psi[nb.at(i, +1)];
     float den = 0.f, n0 = 0.f, n1 = 0.f;
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-        if (!((m >> i) & 1u)) {
-            const float2 r = psi[nb.at(i, +1)];
-            den += weight(i);
-            n0 += weight(i) * r.x;
-            n1 += weight(i) * r.y;
-        }
+    for (int i = 1; i < Q; ++i) {
+        const bool fluid = !((m >> i) & 1u);
+        den += fluid ? weight(i) : 0.0f;
+        n0 += fluid ? weight(i) * r[i].x : 0.0f;
+        n1 += fluid ? weight(i) * r[i].y : 0.0f;
+    }
     const float inv = 1.0f / den;
     const float v = xil[k];
     grad_acc[k] += (double)(pb.x * n0 * inv) - (double)(pb.y * n1 * inv);
@@ -328,13 +332,17 @@ __global__ __launch_bounds__(256) void k_adj_rho(const uint32_t* __restrict__ nb
     const uint32_t m = nbm[nb.idx];
     if (m & SELF_SOLID) return;
     float2 r = psi_adjoint(abar, nb, (size_t)g.n);
+    // all neighbour loads issued together (nbar is read-only here); fluid
+    // neighbours are dropped by a select
+    float2 nv[Q];
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-        if ((m >> i) & 1u) {
-            const float2 nv = nbar[nb.at(i, +1)];
-            r.x += weight(i) * nv.x;
-            r.y += weight(i) * nv.y;
-        }
+    for (int i = 1; i < Q; ++i) nv[i] = nbar[nb.at(i, +1)];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const bool solid = (m >> i) & 1u;
+        r.x += solid ? weight(i) * nv[i].x : 0.0f;
+        r.y += solid ? weight(i) * nv[i].y : 0.0f;
+    }
     rbar[nb.idx] = r;
 }
 

@@ -265,25 +265,34 @@ __device__ __forceinline__ void collide(float (&f)[2][Q], const float (&rho)[2],
     const float om = 1.0f / tau_s;
     const float cf = 1.0f - 0.5f * om;
     const float keep = 1.0f - om;
-    const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+    // Per pair and component, with X = 1 + 4.5 (e.u)^2 - 1.5 u^2 and
+    // t = 3 (e.u)(e.F) - u.F:
+    //   om f^eq + cf S = A X + B t   (even part),  A 3 e.u + B e.F  (odd part),
+    // A = om w rho^(sigma), B = 3 cf w; the odd part flips sign between the
+    // two directions of a pair.
+    const float c1 = 1.0f - 1.5f * (ux * ux + uy * uy + uz * uz);
+    float A[2][2], uF[2];
+    const float B[2] = {3.0f * cf * weight(1), 3.0f * cf * weight(7)};   // axis, diagonal pairs
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const float uF = ux * F[s][0] + uy * F[s][1] + uz * F[s][2];
-        const float r = rho[s];
+        A[s][0] = om * weight(1) * rho[s];
+        A[s][1] = om * weight(7) * rho[s];
+        uF[s] = ux * F[s][0] + uy * F[s][1] + uz * F[s][2];
+    }
 #pragma unroll
-        for (int i = 1; i < Q; i += 2) {
-            const float w = weight(i);
-            const float eu = DX[i] * ux + DY[i] * uy + DZ[i] * uz;
+    for (int i = 1; i < Q; i += 2) {
+        const int c = i < 7 ? 0 : 1;
+        const float eu = DX[i] * ux + DY[i] * uy + DZ[i] * uz;
+        const float eu3 = 3.0f * eu;
+        const float X = fmaf(1.5f * eu, eu3, c1);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
             const float eF = DX[i] * F[s][0] + DY[i] * F[s][1] + DZ[i] * F[s][2];
-            // f^eq = w r (1 + 3 eu + 4.5 eu^2 - 1.5 u^2),  S = w (3 (eF - uF) + 9 eu eF)
-            const float eq_even = w * r * (1.0f + 4.5f * eu * eu - usq15);
-            const float eq_odd = w * r * 3.0f * eu;
-            const float s_even = w * (9.0f * eu * eF - 3.0f * uF);
-            const float s_odd = w * 3.0f * eF;
-            const float g_even = om * eq_even + cf * s_even;
-            const float g_odd = om * eq_odd + cf * s_odd;
-            f[s][i] = keep * f[s][i] + (g_even + g_odd);
-            f[s][i + 1] = keep * f[s][i + 1] + (g_even - g_odd);
+            const float t = fmaf(eu3, eF, -uF[s]);
+            const float ge = fmaf(A[s][c], X, B[c] * t);
+            const float go = fmaf(A[s][c], eu3, B[c] * eF);
+            f[s][i] = fmaf(keep, f[s][i], ge + go);
+            f[s][i + 1] = fmaf(keep, f[s][i + 1], ge - go);
         }
     }
 }

@@ -233,25 +233,57 @@ __device__ __forceinline__ int active_of_block(int nactive) {
     return a < nactive ? a : -1;
 }
 
-// Stage values of planes z0-1 .. z0+2 over the tile plus a one-node halo.
+// Stage values of planes z0-1 .. z0+2 over the tile plus a one-node halo
+// (HZ x HY rows of HX values).  Wave w copies rows w, w + 4, ...: lane l
+// takes column l of each, and lanes 0 .. 2*RPW-1 take the two end columns
+// 64-65 of those rows.  All loads of a thread are issued before the first
+// LDS write, so they are in flight together (and with any loads the caller
+// issued before).  Coordinates wrap periodically once; a position one wrap
+// cannot bring inside the lattice (extents below the tile size) gets the
+// fill value.
 template <class T, class Src>
 __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, int z0, const Geo& g, Src src,
                                            T fill) {
-    const int nxy = g.nx * g.ny;
-    int zs[HZ];
-#pragma unroll
-    for (int p = 0; p < HZ; ++p) zs[p] = ((z0 - 1 + p + g.nz) % g.nz) * nxy;
-    for (int k = threadIdx.x; k < HZ * HX * HY; k += NT) {
-        const int pl = k / (HX * HY);
-        const int r = k - pl * (HX * HY);
-        const int hy = r / HX, hx = r - hy * HX;
-        int gx = x0 + hx - 1, gy = y0 + hy - 1;
-        gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+    constexpr int NW = NT / 64;
+    constexpr int RPW = HZ * HY / NW;  // rows per wave
+    static_assert(HZ * HY % NW == 0 && 2 * RPW <= 64 && HX == 66, "halo row split");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    auto row_base = [&](int r, bool& ok) {
+        const int pl = r / HY, hy = r - pl * HY;
+        int gy = y0 + hy - 1, gz = z0 - 1 + pl;
         gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-        T v = fill;
-        if (gx < g.nx && gy < g.ny) v = src((uint32_t)(gx + g.nx * gy + zs[pl]));
-        tile[pl][hy][hx] = v;
+        gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
+        ok = gy < g.ny;
+        return (uint32_t)(g.nx * (gy + g.ny * gz));
+    };
+    int gx = x0 + lane - 1;
+    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+    const bool inx = gx < g.nx;
+    const bool has_tail = lane < 2 * RPW;
+    const int tp = lane >> 1;                         // row slot of this lane's end-column value
+    int gxt = x0 + 63 + (lane & 1);
+    gxt = gxt >= g.nx ? gxt - g.nx : gxt;
+    T v[RPW];
+    uint32_t rbt = 0;
+    bool okt = false;
+#pragma unroll
+    for (int p = 0; p < RPW; ++p) {
+        bool ok;
+        const uint32_t rb = row_base(wave + NW * p, ok);
+        v[p] = (ok && inx) ? src(rb + (uint32_t)gx) : fill;
+        rbt = tp == p ? rb : rbt;
+        okt = tp == p ? ok : okt;
     }
+    T vt = fill;
+    if (has_tail && okt && gxt < g.nx) vt = src(rbt + (uint32_t)gxt);
+#pragma unroll
+    for (int p = 0; p < RPW; ++p) {
+        const int r = wave + NW * p;
+        tile[r / HY][r % HY][lane] = v[p];
+    }
+    const int rt = wave + NW * tp;
+    if (has_tail) tile[rt / HY][rt % HY][64 + (lane & 1)] = vt;
 }
 
 // Position of a fluid node inside its tile.
