@@ -116,22 +116,6 @@ __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* 
     if (threadIdx.x == 0) bad[blockIdx.x] = any_bad;
 }
 
-// ---------------------------------------------------------------------------
-// Tiles: 64 x 4 x 2 nodes, numbered x fastest, then y, then z.  A tile's
-// fluid nodes are handled by 256 threads, two nodes per thread at most.
-// ---------------------------------------------------------------------------
-constexpr int TX = 64, TY = 4, TZ = 2;
-constexpr int TN = TX * TY * TZ;   // nodes per tile
-constexpr int NT = 256;            // threads per block of the tile kernels
-constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
-
-__device__ __forceinline__ void tile_origin(int t, const Geo& g, int& x0, int& y0, int& z0) {
-    const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
-    x0 = (t % ntx) * TX;
-    y0 = ((t / ntx) % nty) * TY;
-    z0 = (t / (ntx * nty)) * TZ;
-}
-
 // Per tile: number of fluid nodes (into cnt and, for the scans, into base
 // and active_flag).  Block = (64, 4, 2), one thread per tile node.
 __global__ void k_tile_count(const uint32_t* __restrict__ nbm, Geo g, int* __restrict__ cnt,
@@ -220,18 +204,9 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* _
 }
 
 // ---------------------------------------------------------------------------
-// Tile kernels.  One block of 256 threads per active tile; thread j handles
-// the tile's fluid nodes j and j + 256 (when they exist).  Blocks are
-// numbered on a 1D grid and mapped XCD-aware: the hardware deals
-// consecutive block ids round-robin to the 8 XCDs, so block b takes active
-// tile (b mod 8) * per + b / 8 and each XCD works through a contiguous run
-// of neighbouring tiles, whose shared halo rows then hit in that XCD's L2.
+// Tile kernels.  One block of 256 threads per active tile (lbm_tiles.hpp);
+// thread j handles the tile's fluid nodes j and j + 256 (when they exist).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int active_of_block(int nactive) {
-    const int per = gridDim.x >> 3;
-    const int a = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    return a < nactive ? a : -1;
-}
 
 // Stage values of planes z0-1 .. z0+2 over the tile plus a one-node halo
 // (HZ x HY rows of HX values).  Wave w copies rows w, w + 4, ...: lane l
@@ -286,11 +261,7 @@ __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, in
     if (has_tail) tile[rt / HY][rt % HY][64 + (lane & 1)] = vt;
 }
 
-// Position of a fluid node inside its tile.
-struct TilePos {
-    int lx, ly, lz;
-    __device__ __forceinline__ explicit TilePos(int p) : lx(p & (TX - 1)), ly((p / TX) & (TY - 1)), lz(p / (TX * TY)) {}
-};
+
 
 // K1: densities.  psi[x] = (rho1, rho2) at fluid nodes.
 // 8 waves per SIMD (the density pass needs about 50 VGPRs).
@@ -337,15 +308,19 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
     const int z = idx / (g.nx * g.ny);
     const Nb nb(x, y, z, g);
     const uint32_t m = nbm[idx];
+    // all 18 neighbour loads issued together: a solid neighbour reads the
+    // node's own entry instead (a value only this thread writes, after the
+    // loads) and its term is dropped by a select
+    float2 r[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) r[i] = ld((const float2*)psi, ((m >> i) & 1u) ? (uint32_t)idx : nb.at(i, +1));
     float den = 0.f, n0 = 0.f, n1 = 0.f;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        if (!((m >> i) & 1u)) {
-            const float2 r = ld((const float2*)psi, nb.at(i, +1));
-            den += weight(i);
-            n0 += weight(i) * r.x;
-            n1 += weight(i) * r.y;
-        }
+        const bool fluid = !((m >> i) & 1u);
+        den += fluid ? weight(i) : 0.0f;
+        n0 += fluid ? weight(i) * r[i].x : 0.0f;
+        n1 += fluid ? weight(i) * r[i].y : 0.0f;
     }
     const float v = xil[k];
     const float inv = 1.0f / den;  // den > 0: the list holds only nodes with a fluid neighbour
@@ -576,7 +551,6 @@ void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const in
                        active);
 }
 
-static unsigned xcd_grid(int nactive) { return (unsigned)(((nactive + 7) / 8) * 8); }
 
 template <class C>
 void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,

@@ -1,7 +1,7 @@
 // Host-side launchers of the step kernels (implemented in lbm_kernels.hip).
 #pragma once
 
-#include "lbm_device.hpp"
+#include "lbm_tiles.hpp"
 
 namespace mclbm {
 

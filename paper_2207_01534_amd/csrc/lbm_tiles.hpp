@@ -1,0 +1,43 @@
+// Tile geometry shared by the tile-sparse kernels of the step and of its
+// adjoint: the lattice is cut into tiles of 64 x 4 x 2 nodes, numbered x
+// fastest, then y, then z; only tiles holding fluid are launched, one block
+// of 256 threads each, and a tile's fluid nodes are compacted (fluid ids
+// tile base + rank, x fastest inside the tile).
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace mclbm {
+
+constexpr int TX = 64, TY = 4, TZ = 2;
+constexpr int TN = TX * TY * TZ;   // nodes per tile
+constexpr int NT = 256;            // threads per block of the tile kernels
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+
+__device__ __forceinline__ void tile_origin(int t, const Geo& g, int& x0, int& y0, int& z0) {
+    const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
+    x0 = (t % ntx) * TX;
+    y0 = ((t / ntx) % nty) * TY;
+    z0 = (t / (ntx * nty)) * TZ;
+}
+
+// Blocks are numbered on a 1D grid (a multiple of 8 blocks) and mapped
+// XCD-aware: the hardware deals consecutive block ids round-robin to the 8
+// XCDs, so block b takes active tile (b mod 8) * per + b / 8 and each XCD
+// works through a contiguous run of neighbouring tiles, whose shared halo
+// rows then hit in that XCD's L2.  Returns -1 past the last active tile.
+__device__ __forceinline__ int active_of_block(int nactive) {
+    const int per = gridDim.x >> 3;
+    const int a = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    return a < nactive ? a : -1;
+}
+
+// Position of a fluid node inside its tile.
+struct TilePos {
+    int lx, ly, lz;
+    __device__ __forceinline__ explicit TilePos(int p) : lx(p & (TX - 1)), ly((p / TX) & (TY - 1)), lz(p / (TX * TY)) {}
+};
+
+inline unsigned xcd_grid(int nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
+
+}  // namespace mclbm
