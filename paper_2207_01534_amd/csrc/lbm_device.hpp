@@ -50,6 +50,16 @@ __device__ __forceinline__ void st(T* base, uint32_t i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
+// The same at an element offset that may exceed 2^30 (scaled in 64 bits).
+template <class T>
+__device__ __forceinline__ T ld_far(const T* base, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)i * sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st_far(T* base, uint32_t i, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)i * sizeof(T)) = v;
+}
+
 // Node index and periodic neighbour offsets of one node.
 struct Nb {
     uint32_t idx;
@@ -149,38 +159,67 @@ struct Pops {
 // FidAt(i, s) returns the fluid id of x + s e_i, or -1 if it is solid.
 // ---------------------------------------------------------------------------
 
+// Stored values of the 19 incoming populations of both components at one
+// fluid node: the moving ones in the codec's type, the rest ones in FP32.
+template <class C>
+struct RawNode {
+    typename C::T h[2][Q];  // h[.][0] unused
+    float rest[2];
+};
+
+// Issue the loads of fluid node k's incoming populations (no decoding).
+template <class C, bool ODD, class FidAt>
+__device__ __forceinline__ void load_raw(RawNode<C>& r, const Pops<C>& P, uint32_t k, FidAt fid_at, int np) {
+    r.rest[0] = ld(P.rest, k);
+    r.rest[1] = ld(P.rest + np, k);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if constexpr (!ODD) {
+            r.h[0][i] = ld(P.plane(0, i, np), k);
+            r.h[1][i] = ld(P.plane(1, i, np), k);
+        } else {
+            // slot (opp i, src) or, across a wall, (i, k); directions 2k-1, 2k
+            // have adjacent planes, so both are one offset from the lower one
+            const int src = fid_at(i, -1);
+            const bool wall = src < 0;
+            const int lo = (i & 1) ? i : i - 1;
+            const uint32_t e = wall ? k + ((i & 1) ? 0u : (uint32_t)np) : (uint32_t)src + ((i & 1) ? (uint32_t)np : 0u);
+            r.h[0][i] = ld_far(P.plane(0, lo, np), e);
+            r.h[1][i] = ld_far(P.plane(1, lo, np), e);
+        }
+    }
+}
+
+// Decode a loaded node.  RefAt(i, solid) returns the previous-level
+// densities of the node that wrote f_i(x): x - e_i, or x itself when x - e_i
+// is solid (F16/BF16 only); nbm is the node's neighbourhood word.
+template <class C, class RefAt>
+__device__ __forceinline__ void decode_node(float (&f)[2][Q], const RawNode<C>& r, uint32_t nbm, RefAt ref_at) {
+    f[0][0] = r.rest[0];
+    f[1][0] = r.rest[1];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if constexpr (C::kRef) {
+            const float2 rw = ref_at(i, (bool)((nbm >> opp(i)) & 1u));
+            const float rt = rw.x + rw.y;
+            f[0][i] = C::dec(r.h[0][i], weight(i), rw.x, rt);
+            f[1][i] = C::dec(r.h[1][i], weight(i), rw.y, rt);
+        } else {
+            f[0][i] = C::dec(r.h[0][i], weight(i), 0.0f, 0.0f);
+            f[1][i] = C::dec(r.h[1][i], weight(i), 0.0f, 0.0f);
+        }
+    }
+}
+
 // Load and decode the 19 incoming populations of both components at fluid
-// node k.  rprev: densities of the previous time level (F16/BF16 only);
-// nbm: the node's neighbourhood word (F16/BF16 only).
+// node k, with the previous-level densities read from the dense field rprev
+// (F16/BF16 only).
 template <class C, bool ODD, class FidAt>
 __device__ __forceinline__ void load_node(float (&f)[2][Q], const Pops<C>& P, const float2* rprev,
                                           uint32_t nbm, const Nb& nb, uint32_t k, FidAt fid_at, int np) {
-    f[0][0] = ld(P.rest, k);
-    f[1][0] = ld(P.rest + np, k);
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        typename C::T h0, h1;
-        if constexpr (!ODD) {
-            h0 = ld(P.plane(0, i, np), k);
-            h1 = ld(P.plane(1, i, np), k);
-        } else {
-            const int src = fid_at(i, -1);
-            const bool wall = src < 0;
-            const uint32_t at = wall ? k : (uint32_t)src;
-            h0 = ld(wall ? P.plane(0, i, np) : P.plane(0, opp(i), np), at);
-            h1 = ld(wall ? P.plane(1, i, np) : P.plane(1, opp(i), np), at);
-        }
-        if constexpr (C::kRef) {
-            const bool src_solid = (nbm >> opp(i)) & 1u;
-            const float2 rw = ld(rprev, src_solid ? nb.idx : nb.at(i, -1));
-            const float rt = rw.x + rw.y;
-            f[0][i] = C::dec(h0, weight(i), rw.x, rt);
-            f[1][i] = C::dec(h1, weight(i), rw.y, rt);
-        } else {
-            f[0][i] = C::dec(h0, weight(i), 0.0f, 0.0f);
-            f[1][i] = C::dec(h1, weight(i), 0.0f, 0.0f);
-        }
-    }
+    RawNode<C> r;
+    load_raw<C, ODD>(r, P, k, fid_at, np);
+    decode_node<C>(f, r, nbm, [&](int i, bool solid) { return ld(rprev, solid ? nb.idx : nb.at(i, -1)); });
 }
 
 // Sum of populations in a fixed order (shared by every kernel that needs the
@@ -216,11 +255,13 @@ __device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C
             st(D.plane(0, opp(i), np), k, h0);
             st(D.plane(1, opp(i), np), k, h1);
         } else {
+            // slot (i, dst) or, across a wall, (opp i, k), from the pair's lower plane
             const int dst = fid_at(i, +1);
             const bool wall = dst < 0;
-            const uint32_t at = wall ? k : (uint32_t)dst;
-            st(wall ? D.plane(0, opp(i), np) : D.plane(0, i, np), at, h0);
-            st(wall ? D.plane(1, opp(i), np) : D.plane(1, i, np), at, h1);
+            const int lo = (i & 1) ? i : i - 1;
+            const uint32_t e = wall ? k + ((i & 1) ? (uint32_t)np : 0u) : (uint32_t)dst + ((i & 1) ? 0u : (uint32_t)np);
+            st_far(D.plane(0, lo, np), e, h0);
+            st_far(D.plane(1, lo, np), e, h1);
         }
         sum0 += C::dec(h0, weight(i), rho_ref.x, rt);
         sum1 += C::dec(h1, weight(i), rho_ref.y, rt);

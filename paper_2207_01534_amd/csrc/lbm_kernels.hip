@@ -220,8 +220,8 @@ template <class T, class Src>
 __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, int z0, const Geo& g, Src src,
                                            T fill) {
     constexpr int NW = NT / 64;
-    constexpr int RPW = HZ * HY / NW;  // rows per wave
-    static_assert(HZ * HY % NW == 0 && 2 * RPW <= 64 && HX == 66, "halo row split");
+    constexpr int RPW = (HZ * HY + NW - 1) / NW;  // rows per wave (the last ones may run past HZ*HY)
+    static_assert(2 * RPW <= 64 && HX == 66, "halo row split");
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     auto row_base = [&](int r, bool& ok) {
@@ -245,7 +245,9 @@ __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, in
 #pragma unroll
     for (int p = 0; p < RPW; ++p) {
         bool ok;
-        const uint32_t rb = row_base(wave + NW * p, ok);
+        const int r = wave + NW * p;
+        const uint32_t rb = row_base(r < HZ * HY ? r : 0, ok);
+        ok = ok && r < HZ * HY;
         v[p] = (ok && inx) ? src(rb + (uint32_t)gx) : fill;
         rbt = tp == p ? rb : rbt;
         okt = tp == p ? ok : okt;
@@ -255,20 +257,34 @@ __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, in
 #pragma unroll
     for (int p = 0; p < RPW; ++p) {
         const int r = wave + NW * p;
-        tile[r / HY][r % HY][lane] = v[p];
+        if (r < HZ * HY) tile[r / HY][r % HY][lane] = v[p];
     }
     const int rt = wave + NW * tp;
-    if (has_tail) tile[rt / HY][rt % HY][64 + (lane & 1)] = vt;
+    if (has_tail && rt < HZ * HY) tile[rt / HY][rt % HY][64 + (lane & 1)] = vt;
 }
 
 
 
-// K1: densities.  psi[x] = (rho1, rho2) at fluid nodes.
-// 8 waves per SIMD (the density pass needs about 50 VGPRs).
+// Fluid ids of the staged halo around one tile node: fid of x + s e_i, -1
+// at solid nodes.
+struct HaloFid {
+    const int (*t)[HY][HX];
+    int tx, ty, tz;
+    __device__ __forceinline__ int operator()(int i, int s) const {
+        return t[tz + s * DZ[i]][ty + s * DY[i]][tx + s * DX[i]];
+    }
+};
+
+// K1: densities.  psi[x] = (rho1, rho2) at fluid nodes.  In odd steps the
+// fluid-id halo is staged first (the gathers need it); with the F16/BF16
+// codecs the previous-level densities that decode the stored values are
+// staged as an LDS halo as well, while the thread's first node is loaded.
+// At least 8 waves per SIMD in even steps (7 with a decoding halo) and 6
+// in odd steps; the compiler's default schedule would hold ~105 VGPRs.
 template <class C, bool ODD>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm,
-                                                const float2* __restrict__ rprev, float2* __restrict__ psi,
-                                                Geo g) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 6 : (C::kRef ? 7 : 8))))
+void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
+               float2* __restrict__ psi, Geo g) {
     const int a = active_of_block(S.nactive);
     if (a < 0) return;
     const int t = S.active[a];
@@ -276,23 +292,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     tile_origin(t, g, x0, y0, z0);
     const int base = S.base[t], count = S.count[t];
     __shared__ int fidt[ODD ? HZ : 1][HY][HX];
+    __shared__ float2 reft[C::kRef ? HZ : 1][HY][HX];
     if constexpr (ODD) {
         stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
         __syncthreads();
     }
-    for (int j = threadIdx.x; j < count; j += NT) {
+    auto fetch = [&](int j, RawNode<C>& r, TilePos& q) {
         const uint32_t k = (uint32_t)(base + j);
-        const TilePos q(S.loc[k]);
-        const Nb nb(x0 + q.lx, y0 + q.ly, z0 + q.lz, g);
-        const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
+        q = TilePos(S.loc[k]);
+        load_raw<C, ODD>(r, P, k, HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1}, g.np);
+    };
+    auto finish = [&](const RawNode<C>& r, const TilePos& q) {
+        const uint32_t idx = (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)));
+        const uint32_t m = C::kRef ? ld(nbm, idx) : 0u;
+        const int tx = q.lx + 1, ty = q.ly + 1, tz = q.lz + 1;
         float f[2][Q];
-        auto fid_at = [&](int i, int s) {
-            return fidt[1 + q.lz + s * DZ[i]][1 + q.ly + s * DY[i]][1 + q.lx + s * DX[i]];
-        };
-        load_node<C, ODD>(f, P, rprev, m, nb, k, fid_at, g.np);
-        st(psi, nb.idx, make_float2(sum19(f[0]), sum19(f[1])));
+        decode_node<C>(f, r, m, [&](int i, bool solid) {
+            return solid ? reft[tz][ty][tx] : reft[tz - DZ[i]][ty - DY[i]][tx - DX[i]];
+        });
+        st(psi, idx, make_float2(sum19(f[0]), sum19(f[1])));
+    };
+    const int j0 = threadIdx.x;
+    RawNode<C> r;
+    TilePos q(0);
+    if (j0 < count) fetch(j0, r, q);
+    if constexpr (C::kRef) {
+        stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
+        __syncthreads();
+    }
+    if (j0 < count) finish(r, q);
+    for (int j = j0 + NT; j < count; j += NT) {
+        fetch(j, r, q);
+        finish(r, q);
     }
 }
+
 
 // K1b: IVSD virtual solid density at boundary solid nodes (Eqs. 14-15):
 // rho~^(s) = chi^(s) sum_i w_i rho^(s)(x+e_i) [fluid] / sum_i w_i [fluid],
@@ -327,16 +361,6 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
     psi[idx] = make_float2((1.0f + v) * n0 * inv, (1.0f - v) * n1 * inv);
 }
 
-// Fluid ids of the staged halo around one tile node: fid of x + s e_i, -1
-// at solid nodes.
-struct HaloFid {
-    const int (*t)[HY][HX];
-    int tx, ty, tz;
-    __device__ __forceinline__ int operator()(int i, int s) const {
-        return t[tz + s * DZ[i]][ty + s * DY[i]][tx + s * DX[i]];
-    }
-};
-
 // K2: fused force + collision + streaming for the fluid nodes of one tile.
 // The psi-hat values (and, in odd steps, the fluid ids) of planes z0-1 ..
 // z0+2 over the tile and a one-node halo are staged in LDS; each node then
@@ -368,16 +392,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 5)
         stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
         __syncthreads();
     }
-    auto fetch = [&](int j, float (&f)[2][Q], HaloFid& h) {
+    __shared__ float2 reft[C::kRef ? HZ : 1][HY][HX];
+    auto fetch = [&](int j, RawNode<C>& r, HaloFid& h) {
         const uint32_t k = (uint32_t)(base + j);
         const TilePos q(S.loc[k]);
         h = HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1};
-        const Nb nb(x0 + q.lx, y0 + q.ly, z0 + q.lz, g);
-        const uint32_t m = C::kRef ? ld(nbm, nb.idx) : 0u;
-        load_node<C, ODD>(f, P, rprev, m, nb, k, h, g.np);
+        load_raw<C, ODD>(r, P, k, h, g.np);
     };
-    auto finish = [&](int j, float (&f)[2][Q], const HaloFid& h) {
+    auto finish = [&](int j, const RawNode<C>& r, const HaloFid& h) {
         const uint32_t k = (uint32_t)(base + j);
+        const uint32_t idx = (uint32_t)(x0 + h.tx - 1 + g.nx * (y0 + h.ty - 1 + g.ny * (z0 + h.tz - 1)));
+        const uint32_t m = C::kRef ? ld(nbm, idx) : 0u;
+        float f[2][Q];
+        decode_node<C>(f, r, m, [&](int i, bool solid) {
+            return solid ? reft[h.tz][h.ty][h.tx] : reft[h.tz - DZ[i]][h.ty - DY[i]][h.tx - DX[i]];
+        });
         const float rho[2] = {sum19(f[0]), sum19(f[1])};
         float acc[2][3];
         psi_sum([&](int i) { return psit[h.tz + DZ[i]][h.ty + DY[i]][h.tx + DX[i]]; }, acc);
@@ -388,15 +417,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 5)
         store_node<C, ODD>(f, D, rho, psit[h.tz][h.ty][h.tx], k, h, g.np);
     };
     const int j0 = threadIdx.x;
-    float f[2][Q];
+    RawNode<C> r;
     HaloFid h;
-    if (j0 < count) fetch(j0, f, h);
+    if (j0 < count) fetch(j0, r, h);
     stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
+    if constexpr (C::kRef)
+        stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
     __syncthreads();
-    if (j0 < count) finish(j0, f, h);
+    if (j0 < count) finish(j0, r, h);
     for (int j = j0 + NT; j < count; j += NT) {
-        fetch(j, f, h);
-        finish(j, f, h);
+        fetch(j, r, h);
+        finish(j, r, h);
     }
 }
 
