@@ -135,22 +135,23 @@ def run_adjoint(steps=500, every=25):
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2207_01534_amd", "csrc", f)
                   for f in ("lbm_device.hpp", "lbm_tiles.hpp", "lbm_kernels.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_step_kernels_f32.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_step_kernels_spheres512.json")
+CODEC = {"f32": "CodecF32", "f16": "CodecF16", "bf16": "CodecBF16"}
 
 
 def measured_traffic(workload_name, storage):
-    """HBM bytes per collide-stream launch from the committed rocprofv3 counter
+    """HBM bytes per collide-stream launch (odd and even launches alternate, so
+    the mean of the two instantiations) from the committed rocprofv3 counter
     summary, or None when it does not cover this workload/storage or the kernel
     sources changed since the counters were taken."""
     import hashlib
-    if storage != "f32" or not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE))
     h = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SOURCES)).hexdigest()
-    if rec.get("kernel_source_sha256") != h or workload_name not in rec["workloads"]:
-        return None
-    ks = [v for k, v in rec["workloads"][workload_name].items() if k.startswith("k_collide_stream")]
-    if not ks:
+    per = rec["workloads"].get(workload_name, {}).get(storage, {})
+    ks = [v for k, v in per.items() if k.startswith(f"k_collide_stream<{CODEC[storage]},")]
+    if rec.get("kernel_source_sha256") != h or len(ks) != 2:
         return None
     return sum(v["read_bytes"] + v["write_bytes"] for v in ks) / len(ks)
 
@@ -247,6 +248,14 @@ def main():
         _log(f"oracle: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
 
     k2 = main_res["collide_stream_gbs"]
+    name = w.name if not args.shape else None
+
+    def traffic_of(res, storage):
+        t = measured_traffic(name, storage)
+        ms = res["kernels_ms_avg"]["collide_stream"]
+        return t, (round(t / (ms * 1e-3) / 1e9, 1) if t else None)
+
+    traffic, traffic_gbs = traffic_of(main_res, args.storage)
     out = {
         "metric": METRIC,
         "value": round(main_res["mlups"], 1),
@@ -264,7 +273,8 @@ def main():
                    "nodes": w.n_nodes, "fluid_nodes": w.n_fluid, "streaming": "single-buffer AA"},
         "roofline": {"bound": "hbm", "achieved": round(k2, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(k2 / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(w.name if not args.shape else None, args.storage),
+                     "traffic": round(traffic) if traffic else None,
+                     "traffic_gbs": traffic_gbs,
                      "kernel": "k_collide_stream",
                      "algorithmic_bytes_per_launch": main_res["collide_stream_bytes_per_launch"]},
         "cpu_baseline": cpu,
@@ -276,6 +286,7 @@ def main():
                          "ms_per_step": round(v["ms_per_step"], 4),
                          "gbs_alg_step": round(v["gbs_alg_step"], 1),
                          "collide_stream_gbs": round(v["collide_stream_gbs"], 1),
+                         "collide_stream_traffic_gbs": traffic_of(v, k)[1],
                          "kernels_ms_avg": {kk: round(vv, 4) for kk, vv in v["kernels_ms_avg"].items()}}
                      for k, v in variants.items()},
     }
