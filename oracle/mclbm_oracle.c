@@ -46,7 +46,26 @@
  *
  * Layout: populations f[sigma][i][idx], idx = x + nx*(y + ny*z), x fastest.
  * Fields: rho[sigma][idx], F[sigma][axis][idx], u[axis][idx].
- * Solid mask: uint8, nonzero = solid.  All directions are periodic.
+ * Solid mask: uint8, nonzero = solid.  All directions are periodic unless
+ * open_x is set.
+ *
+ * Open inlet/outlet planes (open_x = 1; Sec. 2, the inlet and outlet
+ * conditions, and Sec. 4.1): x is not periodic; x = 0 is the inlet plane,
+ * x = nx-1 the outlet plane (both must be fluid, as must x = 1 and x = nx-2).
+ *   - Force sums at a boundary plane: a neighbour outside the domain takes
+ *     psi-hat from its mirror image across the plane (x + e_i with the x
+ *     component of e_i reversed), the pairing printed after Eq. (11).
+ *   - IVSD sums skip neighbours outside the domain.
+ *   - Streaming leaves the populations that would arrive from outside unset;
+ *     after streaming each boundary node is rebuilt:
+ *       inlet, component 1: non-equilibrium extrapolation (NEEM) to the
+ *         imposed density rho_in from the neighbour x_f = (1, y, z):
+ *         f_i = f_i(x_f) + feq_i(rho_in, u_f) - feq_i(rho1(x_f), u_f),
+ *         u_f = (sum_sigma sum_i e_i f_i(x_f)) / (rho1 + rho2)(x_f);
+ *       inlet, component 2: the five populations with e_x = +1 keep the
+ *         values held in `frozen` (the initial state);
+ *       outlet: the same with the roles swapped (component 2 to rho_out
+ *         from x_f = (nx-2, y, z); component 1's e_x = -1 populations held).
  */
 #include <math.h>
 #include <stddef.h>
@@ -65,6 +84,12 @@ typedef struct {
     double tau[2];            /* tau^(1), tau^(2) */
     double G;                 /* G_coh, Eqs. (11) and (13) */
     double g[2][3];           /* body acceleration per component */
+    int32_t open_x;           /* 1: open inlet (x = 0) and outlet (x = nx-1) planes */
+    double rho_in;            /* component-1 density imposed at the inlet plane */
+    double rho_out;           /* component-2 density imposed at the outlet plane */
+    const double *frozen;     /* [2][Q][ny*nz]: populations held at the inlet
+                                 (side 0, component 2) and outlet (side 1,
+                                 component 1); only the entering directions used */
 } orc_params;
 
 /* D3Q19 velocity set and weights exactly as printed under Eq. (2). */
@@ -104,6 +129,22 @@ static size_t neighbour(const orc_params *p, int x, int y, int z, int i, int sgn
 {
     return node(p, wrap(x, sgn * EX[i], p->nx), wrap(y, sgn * EY[i], p->ny),
                 wrap(z, sgn * EZ[i], p->nz));
+}
+
+/* 1 if x + sgn * e_i leaves the domain through an open x plane. */
+static int outside(const orc_params *p, int x, int i, int sgn)
+{
+    int v = x + sgn * EX[i];
+    return p->open_x && (v < 0 || v >= p->nx);
+}
+
+/* The node whose psi-hat stands in for x + e_i: the neighbour itself, or
+ * across an open plane its mirror image (x component of e_i reversed). */
+static size_t psi_neighbour(const orc_params *p, int x, int y, int z, int i)
+{
+    if (outside(p, x, i, +1))
+        return node(p, x - EX[i], wrap(y, EY[i], p->ny), wrap(z, EZ[i], p->nz));
+    return neighbour(p, x, y, z, i, +1);
 }
 
 static size_t nnodes(const orc_params *p) { return (size_t)p->nx * p->ny * p->nz; }
@@ -197,6 +238,7 @@ void orc_pseudopotential(const orc_params *p, const uint8_t *solid, const double
                 }
                 double den = 0.0, num[NC] = {0.0, 0.0};
                 for (int i = 1; i < Q; ++i) {
+                    if (outside(p, x, i, +1)) continue;
                     size_t m = neighbour(p, x, y, z, i, +1);
                     double fluid = solid[m] ? 0.0 : 1.0; /* 1 - phi */
                     den += W[i] * fluid;
@@ -223,7 +265,7 @@ void orc_forces(const orc_params *p, const uint8_t *solid, const double *rho, co
                     double sum[3] = {0.0, 0.0, 0.0};
                     if (!solid[n])
                         for (int i = 1; i < Q; ++i) {
-                            size_t m = neighbour(p, x, y, z, i, +1);
+                            size_t m = psi_neighbour(p, x, y, z, i);
                             double ps = psi[(size_t)sb * N + m];
                             sum[0] += W[i] * ps * EX[i];
                             sum[1] += W[i] * ps * EY[i];
@@ -300,6 +342,49 @@ void orc_init_equilibrium(const orc_params *p, const uint8_t *solid, const doubl
 }
 
 /*
+ * Open-plane rebuild after streaming (open_x): NEEM for the imposed component
+ * and the held populations of the other one, at every fluid node of the
+ * inlet (x = 0) and outlet (x = nx-1) planes.
+ */
+void orc_open_rebuild(const orc_params *p, const uint8_t *solid, double *f)
+{
+    size_t N = nnodes(p);
+    size_t A = (size_t)p->ny * p->nz;
+    for (int side = 0; side < 2; ++side) {
+        int xb = side ? p->nx - 1 : 0;
+        int xf = side ? p->nx - 2 : 1;
+        int sig = side ? 1 : 0;                 /* imposed component */
+        int held = 1 - sig;                      /* component with held populations */
+        int dir_in = side ? -1 : +1;             /* e_x of the entering directions */
+        double rho_b = side ? p->rho_out : p->rho_in;
+        for (int z = 0; z < p->nz; ++z)
+            for (int y = 0; y < p->ny; ++y) {
+                size_t nb = node(p, xb, y, z), nf = node(p, xf, y, z);
+                if (solid[nb]) continue;
+                double rf[NC] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
+                for (int s = 0; s < NC; ++s)
+                    for (int i = 0; i < Q; ++i) {
+                        double fi = f[((size_t)s * Q + i) * N + nf];
+                        rf[s] += fi;
+                        j[0] += EX[i] * fi;
+                        j[1] += EY[i] * fi;
+                        j[2] += EZ[i] * fi;
+                    }
+                double uf[3] = {j[0] / (rf[0] + rf[1]), j[1] / (rf[0] + rf[1]), j[2] / (rf[0] + rf[1])};
+                double eb[Q], ef[Q];
+                orc_equilibrium(rho_b, uf, eb);
+                orc_equilibrium(rf[sig], uf, ef);
+                for (int i = 0; i < Q; ++i)
+                    f[((size_t)sig * Q + i) * N + nb] = f[((size_t)sig * Q + i) * N + nf] + eb[i] - ef[i];
+                size_t a = (size_t)y + (size_t)p->ny * z;
+                for (int i = 0; i < Q; ++i)
+                    if (EX[i] == dir_in)
+                        f[((size_t)held * Q + i) * N + nb] = p->frozen[((size_t)side * Q + i) * A + a];
+            }
+    }
+}
+
+/*
  * One time step, O1-O8.  f_in holds f(t) and is overwritten by the
  * post-collision populations; f_out receives f(t+1).  The scratch field
  * arrays (rho 2N, psi 2N, F 6N, u 3N) are caller-provided so that the last
@@ -345,7 +430,7 @@ void orc_step(const orc_params *p, const uint8_t *solid, const double *xi, doubl
                 for (int s = 0; s < NC; ++s)
                     for (int i = 0; i < Q; ++i) {
                         double v = 0.0;
-                        if (!solid[n]) {
+                        if (!solid[n] && !outside(p, x, i, -1)) {
                             size_t src = neighbour(p, x, y, z, i, -1);
                             if (!solid[src])
                                 v = f_in[((size_t)s * Q + i) * N + src];
@@ -355,6 +440,7 @@ void orc_step(const orc_params *p, const uint8_t *solid, const double *xi, doubl
                         f_out[((size_t)s * Q + i) * N + n] = v;
                     }
             }
+    if (p->open_x) orc_open_rebuild(p, solid, f_out);
 }
 
 /*

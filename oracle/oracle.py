@@ -22,6 +22,10 @@ class _CParams(ctypes.Structure):
         ("tau", ctypes.c_double * 2),
         ("G", ctypes.c_double),
         ("g", (ctypes.c_double * 3) * 2),
+        ("open_x", ctypes.c_int32),
+        ("rho_in", ctypes.c_double),
+        ("rho_out", ctypes.c_double),
+        ("frozen", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -59,6 +63,7 @@ def _lib():
         lib.orc_loss_snw.argtypes = [P, bp, bp, dp]
         lib.orc_loss_snw.restype = ctypes.c_double
         lib.orc_num_threads.restype = ctypes.c_int32
+        lib.orc_open_rebuild.argtypes = [P, bp, dp]
         _LIB = lib
     return _LIB
 
@@ -127,6 +132,7 @@ class Oracle:
         self.F = np.zeros((2, 3) + self.dims)
         self.u = np.zeros((3,) + self.dims)
         self.t = 0
+        self.frozen = None
 
     @property
     def cp(self):
@@ -140,6 +146,21 @@ class Oracle:
 
     def set_state(self, f: np.ndarray):
         self.fa[...] = f
+
+    def set_open_x(self, rho_in: float, rho_out: float):
+        """Open inlet (x = 0) and outlet (x = nx-1) planes from now on: component 1
+        held at rho_in at the inlet, component 2 at rho_out at the outlet (NEEM);
+        the entering populations of the other component keep the values they have
+        now (the first call captures them)."""
+        nz, ny, nx = self.dims
+        if self.frozen is None:
+            self.frozen = np.zeros((2, 19, nz, ny))
+            self.frozen[0] = self.fa[1, :, :, :, 0]      # inlet: component 2
+            self.frozen[1] = self.fa[0, :, :, :, nx - 1]  # outlet: component 1
+        self._cp.open_x = 1
+        self._cp.rho_in = float(rho_in)
+        self._cp.rho_out = float(rho_out)
+        self._cp.frozen = _d(self.frozen)
 
     @property
     def f(self):

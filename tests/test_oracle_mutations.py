@@ -31,12 +31,27 @@ MUTANTS = [
      "double fluid = 1.0;"),
 ]
 
+# planted mistakes in the open inlet/outlet planes, against their own pins
+OPEN_MUTANTS = [
+    ("open_mirror_to_periodic", "    if (outside(p, x, i, +1))\n        return node(p, x - EX[i]",
+     "    if (0 && outside(p, x, i, +1))\n        return node(p, x - EX[i]"),
+    ("open_neem_interior_density", "orc_equilibrium(rho_b, uf, eb);", "orc_equilibrium(rf[sig], uf, eb);"),
+    ("open_held_wrong_directions", "if (EX[i] == dir_in)", "if (EX[i] == -dir_in)"),
+    ("open_neem_velocity_component", "                        j[1] += EY[i] * fi;",
+     "                        j[1] += EX[i] * fi;"),
+]
+
 PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
              os.path.join(ROOT, "tests", "test_oracle_physics.py") + "::test_single_fluid_poiseuille"]
 
 
-@pytest.mark.parametrize("name,orig,planted", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_mistake_is_caught(name, orig, planted, tmp_path):
+OPEN_PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_open.py")]
+
+
+@pytest.mark.parametrize("name,orig,planted,pins",
+                         [m + (PIN_TESTS,) for m in MUTANTS] + [m + (OPEN_PIN_TESTS,) for m in OPEN_MUTANTS],
+                         ids=[m[0] for m in MUTANTS + OPEN_MUTANTS])
+def test_planted_mistake_is_caught(name, orig, planted, pins, tmp_path):
     src = open(SRC).read()
     assert src.count(orig) == 1, name
     mut_src = tmp_path / "mut.c"
@@ -46,5 +61,5 @@ def test_planted_mistake_is_caught(name, orig, planted, tmp_path):
                     "-o", str(lib), "-lm"], check=True)
     env = dict(os.environ, MCLBM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
-                       + PIN_TESTS, cwd=ROOT, env=env, capture_output=True, text=True)
+                       + pins, cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
