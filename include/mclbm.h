@@ -132,6 +132,37 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps);
 /* Completed steps since the last init / set_geometry / load_state. */
 mclbm_status mclbm_get_time(const mclbm_lattice* lat, int64_t* t);
 
+/* Open inlet/outlet planes along x, the drive of the paper's drainage
+ * simulations (Sec. 2, the inlet and outlet boundary conditions; Sec. 4.1).
+ * Planes x = 0 and x = nx-1 become ghost planes outside the physical domain;
+ * the physical inlet is x = 1, the outlet x = nx-2.  Every step then:
+ *   - force sums at the inlet/outlet planes see, for each missing neighbour,
+ *     the pseudopotential of its mirror image across the plane (the pairing
+ *     printed after Eq. 11);
+ *   - after streaming, component 1 at the inlet and component 2 at the
+ *     outlet are rebuilt by non-equilibrium extrapolation to the imposed
+ *     densities rho1_in and rho2_out from the next plane inwards (bare
+ *     barycentric velocity of that plane), so their densities equal the
+ *     imposed values; the other component's five entering populations keep
+ *     the values they had when the planes were first opened.
+ * enable = 1: the first call (from periodic x) checks that planes 0, 1, 2,
+ *   nx-3, nx-2, nx-1 are fluid (MCLBM_EINVAL otherwise; synchronises the
+ *   stream) and captures the held populations from the current state; later
+ *   calls only change rho1_in / rho2_out (e.g. an inlet-density ramp between
+ *   step calls).  Needs an initialised state and nx >= 6; densities must be
+ *   finite and > 0.
+ * enable = 0: periodic x again (the held values are dropped).
+ * Readouts and diagnostics still cover the whole lattice; values on the
+ * ghost planes carry no physical meaning.  The adjoint entry points refuse a
+ * lattice with open planes. */
+mclbm_status mclbm_set_open_x(mclbm_lattice* lat, int32_t enable, double rho1_in, double rho2_out);
+
+/* Mean Eq. (12) pressure over the fluid voxels of the inlet plane x = 1 and
+ * the outlet plane x = nx-2 at the current time level, copied to the host
+ * (synchronises the stream): h_out[0] = P_in, h_out[1] = P_out,
+ * h_out[2] = P_c = P_in - P_out (Sec. 4.1). */
+mclbm_status mclbm_open_x_pressure(mclbm_lattice* lat, double h_out[3]);
+
 /* Readouts of the state at the current time level (pre-collision).
  * Each output is a caller device buffer; 0 is written at solid voxels.
  *   density  float[2][N]     rho^(sigma), Eq. (3)

@@ -13,10 +13,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_adjoint.hip"),
-           os.path.join(CSRC, "mclbm_api.cpp")]
+           os.path.join(CSRC, "lbm_open.hip"), os.path.join(CSRC, "mclbm_api.cpp")]
 HEADERS = [os.path.join(CSRC, "lbm_device.hpp"), os.path.join(CSRC, "lbm_tiles.hpp"),
            os.path.join(CSRC, "lbm_kernels.hpp"),
-           os.path.join(CSRC, "lbm_adjoint.hpp"), os.path.join(ROOT, "include", "mclbm.h")]
+           os.path.join(CSRC, "lbm_adjoint.hpp"), os.path.join(CSRC, "lbm_open.hpp"),
+           os.path.join(ROOT, "include", "mclbm.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

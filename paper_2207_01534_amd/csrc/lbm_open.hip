@@ -1,0 +1,279 @@
+// Open inlet/outlet planes along x (Sec. 2, the inlet and outlet conditions;
+// Sec. 4.1, the drainage drive).
+//
+// The lattice keeps its x extent; planes x = 0 and x = nx-1 become ghost
+// planes outside the physical domain, the physical inlet is x = 1 and the
+// outlet x = nx-2.  The step kernels run unchanged (periodic in x) and two
+// thin-plane kernels make the planes open:
+//   k_open_mirror   after the pseudopotential field is complete: the ghost
+//                   planes take psi-hat of the mirror image of the boundary
+//                   plane's missing neighbours, psi(0) = psi(2) and
+//                   psi(nx-1) = psi(nx-3), so the force sums at x = 1 and
+//                   x = nx-2 see the pairing printed after Eq. (11);
+//   k_open_rebuild  after collision and streaming, per boundary node x_b:
+//                   non-equilibrium extrapolation (NEEM) of the imposed
+//                   component from x_f = x_b +- 1 (component 1 to rho_in at
+//                   the inlet, component 2 to rho_out at the outlet),
+//                     f_i(x_b) = f_i(x_f) + feq_i(rho_b, u_f) - feq_i(rho_f, u_f),
+//                   u_f the bare barycentric velocity at x_f; the other
+//                   component's entering populations (e_x = +1 at the inlet,
+//                   -1 at the outlet) take their held values.  Whatever the
+//                   ghost planes streamed into the boundary planes is thereby
+//                   replaced; the ghost nodes themselves are reset to rest
+//                   equilibrium at their mirrored densities so they stay finite.
+// Planes 0, 1, 2, nx-3, nx-2 and nx-1 must be fluid (checked on the host).
+#include "lbm_open.hpp"
+
+namespace mclbm {
+
+// Slot of f_i(x) at a time level of the given parity (AA pattern, see
+// lbm_device.hpp): the plane's direction index and the fluid id.  Also
+// returns the node whose density normalised the stored value (F16/BF16).
+struct OpenSlot {
+    int dir;
+    uint32_t id;
+    uint32_t writer;
+};
+
+__device__ __forceinline__ OpenSlot slot_of(int i, bool odd, uint32_t k, uint32_t m, const Nb& nb,
+                                            const int* __restrict__ fid) {
+    const bool up_solid = (m >> opp(i)) & 1u;  // x - e_i solid
+    OpenSlot s;
+    s.writer = up_solid ? nb.idx : nb.at(i, -1);
+    if (!odd || up_solid) {
+        s.dir = i;
+        s.id = k;
+    } else {
+        s.dir = opp(i);
+        s.id = (uint32_t)fid[nb.at(i, -1)];
+    }
+    return s;
+}
+
+template <class C>
+__device__ __forceinline__ float read_pop(const Pops<C>& P, int s, const OpenSlot& q, int i, const float2* psi,
+                                          int np) {
+    const typename C::T h = ld(P.plane(s, q.dir, np), q.id);
+    if constexpr (C::kRef) {
+        const float2 r = ld(psi, q.writer);
+        return C::dec(h, weight(i), s ? r.y : r.x, r.x + r.y);
+    } else {
+        return C::dec(h, weight(i), 0.0f, 0.0f);
+    }
+}
+
+// Store f_i of component s; returns the value a decoder will read back.
+template <class C>
+__device__ __forceinline__ float write_pop(const Pops<C>& P, int s, const OpenSlot& q, int i, float v,
+                                           const float2* psi, int np) {
+    float rw = 0.0f, rt = 0.0f, inv = 0.0f;
+    if constexpr (C::kRef) {
+        const float2 r = ld(psi, q.writer);
+        rw = s ? r.y : r.x;
+        rt = r.x + r.y;
+        inv = inv_total(r);
+    }
+    const typename C::T h = C::enc(v, weight(i), rw, inv);
+    st(P.plane(s, q.dir, np), q.id, h);
+    return C::dec(h, weight(i), rw, rt);
+}
+
+// Eq. (2) at one direction.
+__device__ __forceinline__ float feq(int i, float rho, const float (&u)[3], float usq) {
+    const float eu = DX[i] * u[0] + DY[i] * u[1] + DZ[i] * u[2];
+    return weight(i) * rho * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * usq);
+}
+
+__global__ void k_open_mirror(float2* __restrict__ psi, Geo g) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= g.ny * g.nz) return;
+    const uint32_t row = (uint32_t)a * (uint32_t)g.nx;
+    psi[row] = psi[row + 2];
+    psi[row + g.nx - 1] = psi[row + g.nx - 3];
+}
+
+// One thread per (y, z) row and side.  odd: parity of the time level the
+// populations are at (the one just reached); psi: densities of the level
+// before, the codec reference of every value written in the last step.
+template <class C>
+__global__ void k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const uint32_t* __restrict__ nbm,
+                               const float2* __restrict__ psi, const float* __restrict__ held, Geo g, int odd,
+                               float rho_in, float rho_out) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int A = g.ny * g.nz;
+    if (a >= 2 * A) return;
+    const int side = a >= A ? 1 : 0;
+    const int yz = a - side * A;
+    const int y = yz % g.ny, z = yz / g.ny;
+    const int xb = side ? g.nx - 2 : 1, xf = side ? g.nx - 3 : 2, xg = side ? g.nx - 1 : 0;
+    const int imposed = side, other = 1 - side, dir_in = side ? -1 : 1;
+    const float rho_b = side ? rho_out : rho_in;
+    const int np = g.np;
+
+    // populations of x_f at the new level
+    const Nb nf(xf, y, z, g);
+    const uint32_t kf = (uint32_t)fid[nf.idx];
+    const uint32_t mf = nbm[nf.idx];
+    float ff[2][Q];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        ff[s][0] = ld(P.rest + (size_t)s * np, kf);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) ff[s][i] = read_pop<C>(P, s, slot_of(i, odd, kf, mf, nf, fid), i, psi, np);
+    }
+    float rf[2] = {0.f, 0.f}, j[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            rf[s] += ff[s][i];
+            j[0] += DX[i] * ff[s][i];
+            j[1] += DY[i] * ff[s][i];
+            j[2] += DZ[i] * ff[s][i];
+        }
+    const float inv = 1.0f / (rf[0] + rf[1]);
+    const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
+    const float usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+
+    // boundary node
+    const Nb nb(xb, y, z, g);
+    const uint32_t kb = (uint32_t)fid[nb.idx];
+    const uint32_t mb = nbm[nb.idx];
+    float moving = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const float v = ff[imposed][i] + feq(i, rho_b, u, usq) - feq(i, rf[imposed], u, usq);
+        moving += write_pop<C>(P, imposed, slot_of(i, odd, kb, mb, nb, fid), i, v, psi, np);
+    }
+    st(P.rest + (size_t)imposed * np, kb, rho_b - moving);  // exact imposed density
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if (DX[i] == dir_in) {
+            const float v = held[((size_t)side * Q + i) * A + yz];
+            write_pop<C>(P, other, slot_of(i, odd, kb, mb, nb, fid), i, v, psi, np);
+        }
+
+    // ghost node: rest equilibrium at its (mirrored) densities
+    const Nb ng(xg, y, z, g);
+    const uint32_t kg = (uint32_t)fid[ng.idx];
+    const uint32_t mg = nbm[ng.idx];
+    const float2 rg = psi[ng.idx];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const float r = s ? rg.y : rg.x;
+        float sum = 0.f;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) sum += write_pop<C>(P, s, slot_of(i, odd, kg, mg, ng, fid), i, weight(i) * r, psi, np);
+        st(P.rest + (size_t)s * np, kg, r - sum);
+    }
+}
+
+// Mean pressure (Eq. 12) over the fluid nodes of the inlet (x = 1) and outlet
+// (x = nx-2) planes from the densities in psi; one block per side, FP64.
+__global__ void k_open_pressure(const float2* __restrict__ psi, const uint32_t* __restrict__ nbm, Geo g,
+                                float G, double* __restrict__ out) {
+    const int side = blockIdx.x;
+    const int x = side ? g.nx - 2 : 1;
+    double acc = 0.0, cnt = 0.0;
+    for (int a = threadIdx.x; a < g.ny * g.nz; a += blockDim.x) {
+        const uint32_t idx = (uint32_t)x + (uint32_t)a * (uint32_t)g.nx;
+        if (nbm[idx] & SELF_SOLID) continue;
+        const float2 r = psi[idx];
+        acc += (double)(r.x + r.y) / 3.0 + (double)G / 3.0 * (double)r.x * (double)r.y;
+        cnt += 1.0;
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = acc;
+    red[1][threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[side] = red[1][0] > 0.0 ? red[0][0] / red[1][0] : 0.0;
+}
+
+// Held populations: the current values of the entering directions at the
+// boundary planes (inlet: component 2, e_x = +1; outlet: component 1, e_x = -1).
+template <class C>
+__global__ void k_open_capture(Pops<C> P, const int* __restrict__ fid, const uint32_t* __restrict__ nbm,
+                               const float2* __restrict__ rprev, float* __restrict__ held, Geo g, int odd) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int A = g.ny * g.nz;
+    if (a >= 2 * A) return;
+    const int side = a >= A ? 1 : 0;
+    const int yz = a - side * A;
+    const int y = yz % g.ny, z = yz / g.ny;
+    const int other = 1 - side, dir_in = side ? -1 : 1;
+    const Nb nb(side ? g.nx - 2 : 1, y, z, g);
+    const uint32_t kb = (uint32_t)fid[nb.idx];
+    const uint32_t mb = nbm[nb.idx];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        float v = 0.f;
+        if (i > 0 && DX[i] == dir_in) v = read_pop<C>(P, other, slot_of(i, odd, kb, mb, nb, fid), i, rprev, g.np);
+        held[((size_t)side * Q + i) * A + yz] = v;
+    }
+}
+
+// Number of solid nodes on planes 0, 1, 2, nx-3, nx-2, nx-1 (must be zero);
+// one block of 1024 threads.
+__global__ void k_open_check(const uint32_t* __restrict__ nbm, Geo g, int* __restrict__ count) {
+    const int A = g.ny * g.nz;
+    int total = 0;
+    for (int base = 0; base < 6 * A; base += blockDim.x) {
+        const int a = base + threadIdx.x;
+        bool solid = false;
+        if (a < 6 * A) {
+            const int p = a / A, yz = a - p * A;
+            const int x = p < 3 ? p : g.nx - 6 + p;
+            solid = nbm[(uint32_t)x + (uint32_t)yz * (uint32_t)g.nx] & SELF_SOLID;
+        }
+        total += __syncthreads_count(solid);
+    }
+    if (threadIdx.x == 0) *count = total;
+}
+
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(int n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_open_mirror(float2* psi, const Geo& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_open_mirror, dim3(blocks_for(g.ny * g.nz, 256)), dim3(256), 0, s, psi, g);
+}
+
+template <class C>
+void launch_open_rebuild(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* psi, const float* held,
+                         const Geo& g, int odd, float rho_in, float rho_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_open_rebuild<C>, dim3(blocks_for(2 * g.ny * g.nz, 64)), dim3(64), 0, s, P, fid, nbm, psi,
+                       held, g, odd, rho_in, rho_out);
+}
+
+template <class C>
+void launch_open_capture(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, float* held,
+                         const Geo& g, int odd, hipStream_t s) {
+    hipLaunchKernelGGL(k_open_capture<C>, dim3(blocks_for(2 * g.ny * g.nz, 64)), dim3(64), 0, s, P, fid, nbm,
+                       rprev, held, g, odd);
+}
+
+void launch_open_pressure(const float2* psi, const uint32_t* nbm, const Geo& g, float G, double* out,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_open_pressure, dim3(2), dim3(256), 0, s, psi, nbm, g, G, out);
+}
+
+void launch_open_check(const uint32_t* nbm, const Geo& g, int* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_open_check, dim3(1), dim3(1024), 0, s, nbm, g, count);
+}
+
+#define MCLBM_OPEN_INSTANTIATE(C)                                                                              \
+    template void launch_open_rebuild<C>(const Pops<C>&, const int*, const uint32_t*, const float2*,         \
+                                         const float*, const Geo&, int, float, float, hipStream_t);          \
+    template void launch_open_capture<C>(const Pops<C>&, const int*, const uint32_t*, const float2*, float*, \
+                                         const Geo&, int, hipStream_t);
+MCLBM_OPEN_INSTANTIATE(CodecF32)
+MCLBM_OPEN_INSTANTIATE(CodecF16)
+MCLBM_OPEN_INSTANTIATE(CodecBF16)
+
+}  // namespace mclbm

@@ -11,6 +11,7 @@
 
 #include "../../include/mclbm.h"
 #include "lbm_adjoint.hpp"
+#include "lbm_open.hpp"
 #include "lbm_kernels.hpp"
 
 using namespace mclbm;
@@ -38,7 +39,7 @@ size_t elem_bytes(int storage) { return storage == MCLBM_F32 ? 4 : 2; }
 
 struct Layout {
     size_t mv, rest, R0, R1, nbm, list, xil, counts, bad, partial, misc, total;
-    size_t fid, loc, tcnt, tbase, tapos, tact;
+    size_t fid, loc, tcnt, tbase, tapos, tact, held;
     size_t mv_bytes, rest_bytes, r_bytes;
     int np, cap;
 };
@@ -83,6 +84,7 @@ Layout make_layout(const mclbm_params& p) {
     L.tbase = take(nt * sizeof(int));
     L.tapos = take(nt * sizeof(int));
     L.tact = take(nt * sizeof(int));
+    L.held = take((size_t)2 * Q * p.ny * p.nz * sizeof(float));
     L.misc = take(256);
     L.total = off;
     return L;
@@ -121,6 +123,9 @@ struct mclbm_lattice {
     int nactive;
     bool geometry;
     bool initialized;
+    // open inlet/outlet planes along x (lbm_open.hip)
+    bool open = false;
+    float rho_in = 0.f, rho_out = 0.f;
     // per-kernel event pairs recorded by mclbm_step while profiling
     bool profiling = false;
     std::vector<hipEvent_t> ev[3];
@@ -131,7 +136,10 @@ struct mclbm_lattice {
     float* xil() const { return (float*)(ws + L.xil); }
     double* partial() const { return (double*)(ws + L.partial); }
     int* misc_int() const { return (int*)(ws + L.misc); }
-    double* diag_out() const { return (double*)(ws + L.misc + 64); }
+    double* diag_out() const { return (double*)(ws + L.misc + 64); }     // 8 doubles
+    double* open_out() const { return (double*)(ws + L.misc + 128); }    // 2 doubles
+    int* open_count() const { return (int*)(ws + L.misc + 160); }
+    float* held() const { return (float*)(ws + L.held); }
     int* fid() const { return (int*)(ws + L.fid); }
     Sparse sparse() const {
         return Sparse{(const int*)(ws + L.tact), (const int*)(ws + L.tbase), (const int*)(ws + L.tcnt),
@@ -161,6 +169,7 @@ struct mclbm_lattice {
             launch_density<C>(pops<C>(), sparse(), nbm(), rprev, psi, g, odd, stream);
         });
         launch_ivsd(list(), xil(), nbound, nbm(), psi, g, stream);
+        if (open) launch_open_mirror(psi, g, stream);
     }
     void fields(float* o_rho, float* o_u, float* o_F, float* o_P, double* partial, double* out) {
         fill_psi();
@@ -309,15 +318,64 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
             mark(1);
             launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, lat->g, lat->stream);
             mark(1);
+            if (lat->open) launch_open_mirror(psi, lat->g, lat->stream);
             mark(2);
             launch_collide_stream<C>(lat->pops<C>(), lat->pops<C>(), lat->sparse(), lat->nbm(), rprev, psi, lat->g,
                                      lat->ph, odd, lat->stream);
             mark(2);
+            if (lat->open)
+                launch_open_rebuild<C>(lat->pops<C>(), lat->fid(), lat->nbm(), psi, lat->held(), lat->g, 1 - odd,
+                                       lat->rho_in, lat->rho_out, lat->stream);
         });
         lat->t += 1;
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(mark_err);
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_set_open_x(mclbm_lattice* lat, int32_t enable, double rho1_in, double rho2_out) {
+    if (!lat) return fail(MCLBM_EINVAL, "NULL handle");
+    if (!enable) {
+        lat->open = false;
+        return MCLBM_OK;
+    }
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    if (!(rho1_in > 0.0) || !(rho2_out > 0.0) || !std::isfinite(rho1_in) || !std::isfinite(rho2_out))
+        return fail(MCLBM_EINVAL, "imposed densities must be finite and > 0");
+    if (lat->g.nx < 6) return fail(MCLBM_EINVAL, "open x planes need nx >= 6");
+    if (!lat->open) {
+        int solid = 0;
+        launch_open_check(lat->nbm(), lat->g, lat->open_count(), lat->stream);
+        HIP_TRY(hipMemcpyAsync(&solid, lat->open_count(), sizeof(int), hipMemcpyDeviceToHost, lat->stream));
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (solid) return fail(MCLBM_EINVAL, "planes x = 0, 1, 2, nx-3, nx-2, nx-1 must be fluid");
+        const int odd = (int)(lat->t & 1);
+        lat->with_codec([&](auto c) {
+            using C = decltype(c);
+            launch_open_capture<C>(lat->pops<C>(), lat->fid(), lat->nbm(), lat->R(1 - odd), lat->held(), lat->g,
+                                   odd, lat->stream);
+        });
+        HIP_TRY(hipGetLastError());
+    }
+    lat->rho_in = (float)rho1_in;
+    lat->rho_out = (float)rho2_out;
+    lat->open = true;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_open_x_pressure(mclbm_lattice* lat, double h_out[3]) {
+    if (!lat || !h_out) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    if (lat->g.nx < 6) return fail(MCLBM_EINVAL, "open x planes need nx >= 6");
+    lat->fill_psi();
+    launch_open_pressure(lat->R((int)(lat->t & 1)), lat->nbm(), lat->g, lat->ph.G, lat->open_out(), lat->stream);
+    double out[2];
+    HIP_TRY(hipMemcpyAsync(out, lat->open_out(), sizeof(out), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    h_out[0] = out[0];
+    h_out[1] = out[1];
+    h_out[2] = out[0] - out[1];
     return MCLBM_OK;
 }
 
@@ -500,6 +558,7 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
     if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
     if (((uintptr_t)d_ckpt) % kAlign) return fail(MCLBM_EINVAL, "checkpoint buffer must be 256-byte aligned");
     if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    if (lat->open) return fail(MCLBM_EINVAL, "the adjoint covers periodic x only (open planes are enabled)");
     size_t need = 0;
     mclbm_checkpoint_bytes(lat, nsteps, every, &need);
     if (bytes < need) return fail(MCLBM_EINVAL, "checkpoint buffer too small");
@@ -524,6 +583,7 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
     if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
     if (((uintptr_t)d_work) % kAlign || ((uintptr_t)d_ckpt) % kAlign)
         return fail(MCLBM_EINVAL, "work and checkpoint buffers must be 256-byte aligned");
+    if (lat->open) return fail(MCLBM_EINVAL, "the adjoint covers periodic x only (open planes are enabled)");
     if (!lat->initialized || lat->t < nsteps) return fail(MCLBM_ESTATE, "state is not nsteps past the checkpoints");
     const AdjointWork W = adjoint_layout(lat, every, (char*)d_work);
     if (work_bytes < W.total) return fail(MCLBM_EINVAL, "work buffer too small");

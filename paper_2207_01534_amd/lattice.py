@@ -70,6 +70,8 @@ SIGNATURES = [
     ("mclbm_adjoint_work_bytes", _I32, [_VP, _I32, _SZP]),
     ("mclbm_step_checkpointed", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t]),
     ("mclbm_gradient_snw", _I32, [_VP, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    ("mclbm_set_open_x", _I32, [_VP, _I32, ctypes.c_double, ctypes.c_double]),
+    ("mclbm_open_x_pressure", _I32, [_VP, ctypes.POINTER(ctypes.c_double)]),
     ("mclbm_profile", _I32, [_VP, _I32]),
     ("mclbm_profile_read", _I32, [_VP, ctypes.POINTER(ctypes.c_double), _I64P]),
     ("mclbm_destroy", None, [_VP]),
@@ -264,6 +266,20 @@ class Lattice:
                                        _ptr(work), b.value, _ptr(grad)), "gradient_snw")
         self._keep = (reg, work)
         return grad
+
+    # open inlet/outlet planes ------------------------------------------------
+    def set_open_x(self, rho1_in: float, rho2_out: float, enable: bool = True):
+        """Open the x planes (ghost planes 0 and nx-1, inlet x = 1, outlet x = nx-2):
+        component 1 held at rho1_in at the inlet, component 2 at rho2_out at the
+        outlet; the first call captures the other component's entering populations.
+        Later calls change the imposed densities; enable=False makes x periodic again."""
+        _check(_lib.mclbm_set_open_x(self._h, 1 if enable else 0, float(rho1_in), float(rho2_out)), "set_open_x")
+
+    def open_x_pressure(self) -> dict:
+        """Mean Eq. (12) pressure on the inlet and outlet planes and P_c = P_in - P_out."""
+        out = (ctypes.c_double * 3)()
+        _check(_lib.mclbm_open_x_pressure(self._h, out), "open_x_pressure")
+        return {"P_in": out[0], "P_out": out[1], "P_c": out[2]}
 
     # measurement -------------------------------------------------------------
     KERNELS = ("density", "ivsd", "collide_stream")
