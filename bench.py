@@ -135,7 +135,7 @@ def run_adjoint(steps=500, every=25):
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2207_01534_amd", "csrc", f)
                   for f in ("lbm_device.hpp", "lbm_tiles.hpp", "lbm_kernels.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_step_kernels_spheres512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_step_kernels.json")
 CODEC = {"f32": "CodecF32", "f16": "CodecF16", "bf16": "CodecBF16"}
 
 

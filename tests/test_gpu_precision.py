@@ -19,8 +19,9 @@ BARS = {1: dict(e_rho=2e-3, e_u=2e-3, drift=1e-6),      # FP16
 # The sphere-pack drainage moves a sharp front at G = 3.5: there the stored
 # offset is dominated by the forcing term 3 w_i e_i.F of Eq. (9), and FP16's
 # 11-bit significand bounds the velocity error near 2e-3 of the peak velocity
-# (measured 1.9e-3 to 2.2e-3).  That case is reported against a 3e-3 bound;
-# the 2e-3 target applies to the droplet and to the Gaussian-field medium.
+# (measured 1.8e-3 to 2.2e-3 across kernel versions, which change the FP32
+# rounding order).  That case is reported against a 3e-3 bound; the 2e-3
+# target applies to the droplet and to the Gaussian-field medium.
 FRONT_U_BOUND = 3e-3
 NAMES = {0: "f32", 1: "f16", 2: "bf16"}
 
