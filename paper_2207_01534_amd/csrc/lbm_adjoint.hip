@@ -125,29 +125,27 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const int* __restr
 // ---------------------------------------------------------------------------
 // A1: adjoint of streaming and of the local collision at fluid nodes.
 // ---------------------------------------------------------------------------
+// One thread per fluid node, in fluid-id order (node_of: fluid id -> lattice
+// index); Abar stays zero at solid nodes (cleared once per gradient call).
 template <bool ODD>
 __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __restrict__ fid,
+                                                     const int* __restrict__ node_of, int nfluid,
                                                      const uint32_t* __restrict__ nbm,
                                                      const float2* __restrict__ psi,
                                                      const float* __restrict__ lam_next,
                                                      const float2* __restrict__ rbar_next,
                                                      float* __restrict__ lam_cur, float* __restrict__ abar,
                                                      Geo g, Phys ph) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
+    const int kf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kf >= nfluid) return;
+    const int idx = node_of[kf];
+    const int x = idx % g.nx, y = (idx / g.nx) % g.ny, z = idx / (g.nx * g.ny);
     const Nb nb(x, y, z, g);
     const size_t n = (size_t)g.n;
     const uint32_t m = nbm[nb.idx];
-    if (m & SELF_SOLID) {
-        for (int k = 0; k < 6; ++k) abar[k * n + nb.idx] = 0.0f;
-        return;
-    }
     // forward quantities of this node at time t
     float f[2][Q];
-    load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx], [&](int i, int s) { return fid[nb.at(i, s)]; },
-                       g.np);
+    load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)kf, [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
     const float rho[2] = {sum19(f[0]), sum19(f[1])};
     float A[2][3];
     psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, A);
@@ -321,16 +319,15 @@ __global__ __launch_bounds__(256) void k_adj_ivsd(const int* __restrict__ list, 
 // ---------------------------------------------------------------------------
 // A3: non-local density adjoint at fluid nodes.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adj_rho(const uint32_t* __restrict__ nbm, const float* __restrict__ abar,
+__global__ __launch_bounds__(256) void k_adj_rho(const int* __restrict__ node_of, int nfluid,
+                                                 const uint32_t* __restrict__ nbm, const float* __restrict__ abar,
                                                  const float2* __restrict__ nbar, Geo g,
                                                  float2* __restrict__ rbar) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
-    const Nb nb(x, y, z, g);
+    const int kf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kf >= nfluid) return;
+    const int idx = node_of[kf];
+    const Nb nb(idx % g.nx, (idx / g.nx) % g.ny, idx / (g.nx * g.ny), g);
     const uint32_t m = nbm[nb.idx];
-    if (m & SELF_SOLID) return;
     float2 r = psi_adjoint(abar, nb, (size_t)g.n);
     // all neighbour loads issued together (nbar is read-only here); fluid
     // neighbours are dropped by a select
@@ -344,6 +341,14 @@ __global__ __launch_bounds__(256) void k_adj_rho(const uint32_t* __restrict__ nb
         r.y += solid ? weight(i) * nv[i].y : 0.0f;
     }
     rbar[nb.idx] = r;
+}
+
+// node_of[fid[idx]] = idx for every fluid node.
+__global__ void k_node_of(const int* __restrict__ fid, int n, int* __restrict__ node_of) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int k = fid[idx];
+    if (k >= 0) node_of[k] = idx;
 }
 
 __global__ void k_zero_words(uint32_t* __restrict__ p, size_t nwords) {
@@ -386,15 +391,21 @@ void launch_adj_seed(const Pops<CF>& P, const int* fid, const uint32_t* nbm, con
         hipLaunchKernelGGL(k_adj_seed<false>, rows(g), kBlock, 0, s, P, fid, nbm, region, g, loss, lam, rbar);
 }
 
-void launch_adj_collide(const Pops<CF>& P, const int* fid, const uint32_t* nbm, const float2* psi,
-                        const float* lam_next, const float2* rbar_next, float* lam_cur, float* abar, const Geo& g,
-                        const Phys& ph, int odd, hipStream_t s) {
+void launch_node_of(const int* fid, const Geo& g, int* node_of, hipStream_t s) {
+    hipLaunchKernelGGL(k_node_of, dim3((g.n + 255) / 256), dim3(256), 0, s, fid, g.n, node_of);
+}
+
+void launch_adj_collide(const Pops<CF>& P, const int* fid, const int* node_of, int nfluid, const uint32_t* nbm,
+                        const float2* psi, const float* lam_next, const float2* rbar_next, float* lam_cur,
+                        float* abar, const Geo& g, const Phys& ph, int odd, hipStream_t s) {
+    if (nfluid <= 0) return;
+    const dim3 grid((nfluid + 255) / 256);
     if (odd)
-        hipLaunchKernelGGL(k_adj_collide<true>, rows(g), kBlock, 0, s, P, fid, nbm, psi, lam_next, rbar_next,
-                           lam_cur, abar, g, ph);
+        hipLaunchKernelGGL(k_adj_collide<true>, grid, dim3(256), 0, s, P, fid, node_of, nfluid, nbm, psi, lam_next,
+                           rbar_next, lam_cur, abar, g, ph);
     else
-        hipLaunchKernelGGL(k_adj_collide<false>, rows(g), kBlock, 0, s, P, fid, nbm, psi, lam_next, rbar_next,
-                           lam_cur, abar, g, ph);
+        hipLaunchKernelGGL(k_adj_collide<false>, grid, dim3(256), 0, s, P, fid, node_of, nfluid, nbm, psi,
+                           lam_next, rbar_next, lam_cur, abar, g, ph);
 }
 
 void launch_adj_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, const float2* psi,
@@ -404,9 +415,11 @@ void launch_adj_ivsd(const int* list, const float* xil, int count, const uint32_
                        g, grad_acc, nbar);
 }
 
-void launch_adj_rho(const uint32_t* nbm, const float* abar, const float2* nbar, const Geo& g, float2* rbar,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_rho, rows(g), kBlock, 0, s, nbm, abar, nbar, g, rbar);
+void launch_adj_rho(const int* node_of, int nfluid, const uint32_t* nbm, const float* abar, const float2* nbar,
+                    const Geo& g, float2* rbar, hipStream_t s) {
+    if (nfluid <= 0) return;
+    hipLaunchKernelGGL(k_adj_rho, dim3((nfluid + 255) / 256), dim3(256), 0, s, node_of, nfluid, nbm, abar, nbar,
+                       g, rbar);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {

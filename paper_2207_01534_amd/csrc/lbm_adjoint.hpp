@@ -10,13 +10,15 @@ void launch_loss(const Pops<CodecF32>& P, const int* fid, const uint32_t* nbm, c
                  const Geo& g, int odd, double* partial, double* out, hipStream_t s);
 void launch_adj_seed(const Pops<CodecF32>& P, const int* fid, const uint32_t* nbm, const uint8_t* region,
                      const Geo& g, int odd, const double* loss, float* lam, float2* rbar, hipStream_t s);
-void launch_adj_collide(const Pops<CodecF32>& P, const int* fid, const uint32_t* nbm, const float2* psi,
-                        const float* lam_next, const float2* rbar_next, float* lam_cur, float* abar, const Geo& g,
-                        const Phys& ph, int odd, hipStream_t s);
+// node_of[k] = lattice index of fluid id k
+void launch_node_of(const int* fid, const Geo& g, int* node_of, hipStream_t s);
+void launch_adj_collide(const Pops<CodecF32>& P, const int* fid, const int* node_of, int nfluid, const uint32_t* nbm,
+                        const float2* psi, const float* lam_next, const float2* rbar_next, float* lam_cur,
+                        float* abar, const Geo& g, const Phys& ph, int odd, hipStream_t s);
 void launch_adj_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, const float2* psi,
                      const float* abar, const Geo& g, double* grad_acc, float2* nbar, hipStream_t s);
-void launch_adj_rho(const uint32_t* nbm, const float* abar, const float2* nbar, const Geo& g, float2* rbar,
-                    hipStream_t s);
+void launch_adj_rho(const int* node_of, int nfluid, const uint32_t* nbm, const float* abar, const float2* nbar,
+                    const Geo& g, float2* rbar, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_grad_scatter(const int* list, int count, const double* acc, double* grad, hipStream_t s);
 

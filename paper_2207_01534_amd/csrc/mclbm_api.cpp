@@ -521,6 +521,7 @@ struct AdjointWork {
     float2* rbar[2];
     float2* nbar;
     double* gacc;   // per boundary-list entry
+    int* node_of;   // lattice index of each fluid id
     size_t total;
 };
 
@@ -542,6 +543,7 @@ static AdjointWork adjoint_layout(const mclbm_lattice* lat, int32_t every, char*
     w.rbar[1] = (float2*)take(n * sizeof(float2));
     w.nbar = (float2*)take(n * sizeof(float2));
     w.gacc = (double*)take(n * sizeof(double));
+    w.node_of = (int*)take((size_t)lat->L.cap * sizeof(int));
     w.total = off;
     return w;
 }
@@ -597,6 +599,8 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
     const int nseg = (nsteps + every - 1) / every;
 
     launch_zero(W.gacc, (size_t)lat->nbound * sizeof(double), s);
+    launch_zero(W.abar, 6 * n * sizeof(float), s);  // solid entries are never written by the reverse steps
+    launch_node_of(lat->fid(), g, W.node_of, s);
     launch_zero(d_grad_xi, n * sizeof(double), s);
     // seed from the final state (the lattice's current populations)
     launch_loss(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->partial(),
@@ -630,10 +634,10 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
             const Pops<CodecF32> sk = slot_pops(W.seg + (size_t)k * slot, L);
             const float2* psi = (const float2*)(W.psi + (size_t)k * psi_stride);
             const int nxt = cur, now = 1 - cur;
-            launch_adj_collide(sk, lat->fid(), lat->nbm(), psi, W.lam[nxt], W.rbar[nxt], W.lam[now], W.abar, g,
-                               lat->ph, odd, s);
+            launch_adj_collide(sk, lat->fid(), W.node_of, lat->nfluid, lat->nbm(), psi, W.lam[nxt], W.rbar[nxt],
+                               W.lam[now], W.abar, g, lat->ph, odd, s);
             launch_adj_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, W.abar, g, W.gacc, W.nbar, s);
-            launch_adj_rho(lat->nbm(), W.abar, W.nbar, g, W.rbar[now], s);
+            launch_adj_rho(W.node_of, lat->nfluid, lat->nbm(), W.abar, W.nbar, g, W.rbar[now], s);
             cur = now;
         }
     }
