@@ -107,8 +107,8 @@ mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t 
  *          chi^(2) = 1 - xi.  |xi| < 1 required there (EINVAL otherwise).
  * Both are copied into the workspace; the caller may free them afterwards.
  * Builds the sparse storage: populations live only at fluid voxels,
- * compacted within tiles of 64 x 4 voxels of one z plane; tiles without
- * fluid are dropped.  Synchronises the stream.  Resets the step counter to
+ * compacted within tiles of 64 x 4 x 2 voxels; tiles without fluid are
+ * dropped.  Synchronises the stream.  Resets the step counter to
  * 0.  On EINVAL (|xi| >= 1, or more fluid voxels than fluid_capacity) the
  * lattice is left without geometry and set_geometry must be called again. */
 mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, const float* d_xi);
