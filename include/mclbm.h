@@ -152,9 +152,9 @@ mclbm_status mclbm_get_time(const mclbm_lattice* lat, int64_t* t);
  *   step calls).  Needs an initialised state and nx >= 6; densities must be
  *   finite and > 0.
  * enable = 0: periodic x again (the held values are dropped).
- * Readouts and diagnostics still cover the whole lattice; values on the
- * ghost planes carry no physical meaning.  The adjoint entry points refuse a
- * lattice with open planes. */
+ * Readouts still cover the whole lattice (values on the ghost planes carry
+ * no physical meaning); the diagnostics' sums and maxima then leave the ghost
+ * planes out.  The adjoint entry points refuse a lattice with open planes. */
 mclbm_status mclbm_set_open_x(mclbm_lattice* lat, int32_t enable, double rho1_in, double rho2_out);
 
 /* Mean Eq. (12) pressure over the fluid voxels of the inlet plane x = 1 and

@@ -442,7 +442,7 @@ __global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict
                                                     const float2* __restrict__ psi, Geo g, Phys ph,
                                                     float* __restrict__ o_rho, float* __restrict__ o_u,
                                                     float* __restrict__ o_F, float* __restrict__ o_P,
-                                                    double* __restrict__ partial) {
+                                                    double* __restrict__ partial, int skip_ghost_x) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
@@ -469,13 +469,16 @@ __global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict
             pr = (rho[0] + rho[1]) * (1.0f / 3.0f) + (ph.G / 3.0f) * rho[0] * rho[1];
             const double r0 = rho[0], r1 = rho[1];
             const double um = sqrt((double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
-            d[0] = r0;
-            d[1] = r1;
-            d[2] = r1 > r0 ? 1.0 : 0.0;
-            d[3] = r0 / (r0 + r1);
-            d[4] = um;
-            d[5] = (isfinite(rho[0]) && isfinite(rho[1]) && isfinite(um)) ? 0.0 : 1.0;
-            d[6] = 1.0;
+            // with open x planes the ghost planes stay out of the diagnostics
+            if (!(skip_ghost_x && (x == 0 || x == g.nx - 1))) {
+                d[0] = r0;
+                d[1] = r1;
+                d[2] = r1 > r0 ? 1.0 : 0.0;
+                d[3] = r0 / (r0 + r1);
+                d[4] = um;
+                d[5] = (isfinite(rho[0]) && isfinite(rho[1]) && isfinite(um)) ? 0.0 : 1.0;
+                d[6] = 1.0;
+            }
         }
         if (o_rho) { o_rho[self] = rho[0]; o_rho[n + self] = rho[1]; }
         if (o_u) { o_u[self] = u[0]; o_u[n + self] = u[1]; o_u[2 * n + self] = u[2]; }
@@ -629,13 +632,13 @@ int fields_blocks(const Geo& g) {
 template <class C>
 void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, const float2* psi,
                    const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F, float* o_P,
-                   double* partial, double* out, hipStream_t s) {
+                   double* partial, double* out, int skip_ghost_x, hipStream_t s) {
     if (odd)
         hipLaunchKernelGGL((k_fields<C, true>), tile_grid3(g), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
-                           ph, o_rho, o_u, o_F, o_P, partial);
+                           ph, o_rho, o_u, o_F, o_P, partial, skip_ghost_x);
     else
         hipLaunchKernelGGL((k_fields<C, false>), tile_grid3(g), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
-                           ph, o_rho, o_u, o_F, o_P, partial);
+                           ph, o_rho, o_u, o_F, o_P, partial, skip_ghost_x);
     if (partial)
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, (const double*)partial,
                            fields_blocks(g), out);
@@ -651,7 +654,7 @@ void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const 
                                            hipStream_t);                                                  \
     template void launch_fields<C>(const Pops<C>&, const int*, const uint32_t*, const float2*,            \
                                    const float2*, const Geo&, const Phys&, int, float*, float*, float*,   \
-                                   float*, double*, double*, hipStream_t);
+                                   float*, double*, double*, int, hipStream_t);
 
 MCLBM_INSTANTIATE(CodecF32)
 MCLBM_INSTANTIATE(CodecF16)

@@ -46,6 +46,6 @@ int fields_blocks(const Geo& g);
 template <class C>
 void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, const float2* psi,
                    const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F, float* o_P,
-                   double* partial, double* out, hipStream_t s);
+                   double* partial, double* out, int skip_ghost_x, hipStream_t s);
 
 }  // namespace mclbm

@@ -179,7 +179,7 @@ struct mclbm_lattice {
         with_codec([&](auto c) {
             using C = decltype(c);
             launch_fields<C>(pops<C>(), fid(), nbm(), rprev, psi, g, ph, odd, o_rho, o_u, o_F, o_P, partial,
-                             out, stream);
+                             out, open ? 1 : 0, stream);
         });
     }
 };
