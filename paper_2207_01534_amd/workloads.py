@@ -109,7 +109,7 @@ def gaussian_field_medium(shape, ell, porosity, seed, buffer=3):
     ky = np.fft.fftfreq(ny)[None, :, None]
     kx = np.fft.rfftfreq(nx)[None, None, :]
     filt = np.exp(-2.0 * (np.pi * sigma) ** 2 * (kx ** 2 + ky ** 2 + kz ** 2))
-    fieldv = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=(nz, ny, nx))
+    fieldv = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=(nz, ny, nx), axes=(0, 1, 2))
     sample = fieldv[:, :, buffer:nx - buffer]
     thr = np.quantile(sample, porosity)
     solid = (fieldv > thr).astype(np.uint8)
