@@ -210,8 +210,9 @@ mclbm_status mclbm_loss_snw(mclbm_lattice* lat, const uint8_t* d_region, double*
  * steps: ceil(nsteps/every) population states. */
 mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes);
 
-/* Bytes of the work buffer mclbm_gradient_snw needs: `every` recomputed
- * states and psi-hat fields plus the adjoint fields. */
+/* Bytes of the work buffer mclbm_gradient_snw needs: two buffers of `every`
+ * recomputed states and psi-hat fields (one segment is recomputed while the
+ * next is reversed) plus the adjoint fields. */
 mclbm_status mclbm_adjoint_work_bytes(const mclbm_lattice* lat, int32_t every, size_t* bytes);
 
 /* mclbm_step(nsteps) that also copies the state into slot k of d_ckpt
@@ -228,7 +229,11 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
  * of the forced collision, Eqs. 1-2, 6-9, and of the forces and virtual
  * solid densities, Eqs. 10-15).  d_grad_xi: double[N] (output; written in
  * full, non-zero only at solid voxels with a fluid neighbour).  The
- * lattice's state is left unchanged.  Asynchronous on the stream. */
+ * lattice's state is left unchanged.  Asynchronous on the stream: the
+ * segment recomputes run on a second, non-blocking stream that the library
+ * creates on first use (kept until mclbm_destroy), ordered against the
+ * lattice's stream by events; the gradient is complete when the lattice's
+ * stream reaches the end of the call's work. */
 mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
                                 const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi);
 

@@ -41,13 +41,17 @@ __device__ __forceinline__ bool is_boundary_solid(uint32_t m) {
     return (m & SELF_SOLID) && ((~m) & NB_BITS);
 }
 
-constexpr int kListBlock = 256;
-
-__global__ void k_boundary_count(const uint32_t* __restrict__ nbm, int n, int* __restrict__ counts) {
-    const int idx = blockIdx.x * kListBlock + threadIdx.x;
-    const bool flag = idx < n && is_boundary_solid(nbm[idx]);
+// The list of boundary solids is built tile by tile (one block of 64 x 4 x 2
+// threads per tile, every tile of the lattice, in the tiles' numbering), so
+// that consecutive list entries are close in all three directions and the
+// IVSD gathers of a run of entries hit the same psi-hat lines.
+__global__ void k_boundary_count(const uint32_t* __restrict__ nbm, Geo g, int* __restrict__ counts) {
+    int x0, y0, z0;
+    tile_origin(blockIdx.x, g, x0, y0, z0);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y, z = z0 + threadIdx.z;
+    const bool flag = x < g.nx && y < g.ny && z < g.nz && is_boundary_solid(nbm[x + g.nx * (y + g.ny * z)]);
     const int c = __syncthreads_count(flag);
-    if (threadIdx.x == 0) counts[blockIdx.x] = c;
+    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) counts[blockIdx.x] = c;
 }
 
 // Exclusive scan of an int array in place by one block (set-up only); the
@@ -97,11 +101,14 @@ __device__ __forceinline__ int block_rank(bool flag, int* wave_off, int* count) 
 }
 
 __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* __restrict__ xi,
-                                 int n, const int* __restrict__ offsets, int* __restrict__ list,
+                                 Geo g, const int* __restrict__ offsets, int* __restrict__ list,
                                  float* __restrict__ xil, int* __restrict__ bad) {
-    __shared__ int wave_off[kListBlock / 64];
-    const int idx = blockIdx.x * kListBlock + threadIdx.x;
-    const bool flag = idx < n && is_boundary_solid(nbm[idx]);
+    __shared__ int wave_off[TN / 64];
+    int x0, y0, z0;
+    tile_origin(blockIdx.x, g, x0, y0, z0);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y, z = z0 + threadIdx.z;
+    const int idx = x + g.nx * (y + g.ny * z);
+    const bool flag = x < g.nx && y < g.ny && z < g.nz && is_boundary_solid(nbm[idx]);
     int cnt;
     const int rank = block_rank(flag, wave_off, &cnt);
     bool invalid = false;
@@ -113,7 +120,7 @@ __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* 
         invalid = !(fabsf(v) < 1.0f);
     }
     const int any_bad = __syncthreads_or(invalid);
-    if (threadIdx.x == 0) bad[blockIdx.x] = any_bad;
+    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) bad[blockIdx.x] = any_bad;
 }
 
 // Per tile: number of fluid nodes (into cnt and, for the scans, into base
@@ -560,14 +567,14 @@ void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hi
     hipLaunchKernelGGL(k_neighbour_bits, row_grid(g), dim3(64), 0, s, solid, nbm, g);
 }
 
-int boundary_blocks(const Geo& g) { return (g.n + kListBlock - 1) / kListBlock; }
+int boundary_blocks(const Geo& g) { return tile_count(g); }
 
 void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int* total, int* list,
                           float* xil, int* bad, const Geo& g, hipStream_t s) {
     const int nb = boundary_blocks(g);
-    hipLaunchKernelGGL(k_boundary_count, dim3(nb), dim3(kListBlock), 0, s, nbm, g.n, counts);
+    hipLaunchKernelGGL(k_boundary_count, dim3(nb), dim3(TX, TY, TZ), 0, s, nbm, g, counts);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, nb, total);
-    hipLaunchKernelGGL(k_boundary_write, dim3(nb), dim3(kListBlock), 0, s, nbm, xi, g.n,
+    hipLaunchKernelGGL(k_boundary_write, dim3(nb), dim3(TX, TY, TZ), 0, s, nbm, xi, g,
                        (const int*)counts, list, xil, bad);
 }
 

@@ -129,6 +129,10 @@ struct mclbm_lattice {
     // per-kernel event pairs recorded by mclbm_step while profiling
     bool profiling = false;
     std::vector<hipEvent_t> ev[3];
+    // reverse sweep: a second stream (non-blocking, default priority) that
+    // recomputes the next segment while the current one is reversed
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
 
     float2* R(int k) const { return (float2*)(ws + (k ? L.R1 : L.R0)); }
     uint32_t* nbm() const { return (uint32_t*)(ws + L.nbm); }
@@ -514,8 +518,8 @@ mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, in
 }
 
 struct AdjointWork {
-    char* seg;      // every state slots
-    char* psi;      // every psi-hat fields (n float2 each)
+    char* seg[2];   // two segment buffers of `every` state slots
+    char* psi[2];   // and of `every` psi-hat fields (n float2 each)
     float* lam[2];  // [2][19][n]
     float* abar;    // [6][n]
     float2* rbar[2];
@@ -534,8 +538,10 @@ static AdjointWork adjoint_layout(const mclbm_lattice* lat, int32_t every, char*
         return base + at;
     };
     AdjointWork w;
-    w.seg = take((size_t)every * state_slot_bytes(lat->L));
-    w.psi = take((size_t)every * align_up(n * sizeof(float2), kAlign));
+    for (int b = 0; b < 2; ++b) {
+        w.seg[b] = take((size_t)every * state_slot_bytes(lat->L));
+        w.psi[b] = take((size_t)every * align_up(n * sizeof(float2), kAlign));
+    }
     w.lam[0] = (float*)take(2 * Q * n * sizeof(float));
     w.lam[1] = (float*)take(2 * Q * n * sizeof(float));
     w.abar = (float*)take(6 * n * sizeof(float));
@@ -578,6 +584,17 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
     return MCLBM_OK;
 }
 
+// The reverse sweep's auxiliary stream and events, created on first use on
+// the lattice's device and kept until mclbm_destroy.
+static hipError_t ensure_aux(mclbm_lattice* lat) {
+    if (lat->aux) return hipSuccess;
+    hipError_t e = hipStreamCreateWithFlags(&lat->aux, hipStreamNonBlocking);
+    hipEvent_t* evs[5] = {&lat->ev_start, &lat->ev_rec[0], &lat->ev_rec[1], &lat->ev_rev[0], &lat->ev_rev[1]};
+    for (hipEvent_t* p : evs)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(p, hipEventDisableTiming);
+    return e;
+}
+
 mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
                                 const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
     if (!lat || !d_ckpt || !d_region || !d_work || !d_grad_xi || nsteps < 1 || every < 1)
@@ -608,31 +625,57 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
     int cur = 0;  // lam[cur], rbar[cur] hold dL/df at the time level being processed
     launch_adj_seed(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->diag_out(),
                     W.lam[cur], W.rbar[cur], s);
-    for (int seg = nseg - 1; seg >= 0; --seg) {
+    // Segment seg is recomputed into buffer seg & 1 on the auxiliary stream
+    // and reversed from it on the lattice's stream; the recompute of segment
+    // seg - 1 runs while segment seg is reversed (the two touch disjoint
+    // memory; the lattice's geometry and the checkpoints are only read), and
+    // waits for the reverse of segment seg + 1, the last user of its buffer.
+    HIP_TRY(ensure_aux(lat));
+    hipStream_t s2 = lat->aux;
+    HIP_TRY(hipEventRecord(lat->ev_start, s));
+    HIP_TRY(hipStreamWaitEvent(s2, lat->ev_start, 0));
+    auto recompute = [&](int seg) -> mclbm_status {
+        const int b = seg & 1;
         const int64_t ta = t0 + (int64_t)seg * every;
         const int len = (int)((ta + every <= t_end ? ta + every : t_end) - ta);
         const Pops<CodecF32> c = slot_pops((char*)d_ckpt + (size_t)seg * slot, L);
-        const Pops<CodecF32> s0 = slot_pops(W.seg, L);
-        HIP_TRY(hipMemcpyAsync(s0.mv, c.mv, L.mv_bytes, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(s0.rest, c.rest, L.rest_bytes, hipMemcpyDeviceToDevice, s));
-        // recompute the segment's states and their psi-hat fields
+        const Pops<CodecF32> s0 = slot_pops(W.seg[b], L);
+        HIP_TRY(hipMemcpyAsync(s0.mv, c.mv, L.mv_bytes, hipMemcpyDeviceToDevice, s2));
+        HIP_TRY(hipMemcpyAsync(s0.rest, c.rest, L.rest_bytes, hipMemcpyDeviceToDevice, s2));
+        // the segment's states and their psi-hat fields
         for (int k = 0; k < len; ++k) {
             const int odd = (int)((ta + k) & 1);
-            const Pops<CodecF32> sk = slot_pops(W.seg + (size_t)k * slot, L);
-            float2* psi = (float2*)(W.psi + (size_t)k * psi_stride);
+            const Pops<CodecF32> sk = slot_pops(W.seg[b] + (size_t)k * slot, L);
+            float2* psi = (float2*)(W.psi[b] + (size_t)k * psi_stride);
             launch_density<CodecF32>(sk, lat->sparse(), lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g, odd,
-                                     s);
-            launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, g, s);
+                                     s2);
+            launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, g, s2);
             if (k + 1 < len) {
-                const Pops<CodecF32> sn = slot_pops(W.seg + (size_t)(k + 1) * slot, L);
-                launch_collide_stream<CodecF32>(sk, sn, lat->sparse(), lat->nbm(), psi, psi, g, lat->ph, odd, s);
+                const Pops<CodecF32> sn = slot_pops(W.seg[b] + (size_t)(k + 1) * slot, L);
+                launch_collide_stream<CodecF32>(sk, sn, lat->sparse(), lat->nbm(), psi, psi, g, lat->ph, odd, s2);
             }
         }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(lat->ev_rec[b], s2));
+        return MCLBM_OK;
+    };
+    mclbm_status st = recompute(nseg - 1);
+    if (st != MCLBM_OK) return st;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int b = seg & 1;
+        if (seg > 0) {
+            if (seg + 1 < nseg) HIP_TRY(hipStreamWaitEvent(s2, lat->ev_rev[1 - b], 0));
+            st = recompute(seg - 1);
+            if (st != MCLBM_OK) return st;
+        }
+        HIP_TRY(hipStreamWaitEvent(s, lat->ev_rec[b], 0));
+        const int64_t ta = t0 + (int64_t)seg * every;
+        const int len = (int)((ta + every <= t_end ? ta + every : t_end) - ta);
         // reverse steps
         for (int k = len - 1; k >= 0; --k) {
             const int odd = (int)((ta + k) & 1);
-            const Pops<CodecF32> sk = slot_pops(W.seg + (size_t)k * slot, L);
-            const float2* psi = (const float2*)(W.psi + (size_t)k * psi_stride);
+            const Pops<CodecF32> sk = slot_pops(W.seg[b] + (size_t)k * slot, L);
+            const float2* psi = (const float2*)(W.psi[b] + (size_t)k * psi_stride);
             const int nxt = cur, now = 1 - cur;
             launch_adj_collide(sk, lat->fid(), W.node_of, lat->nfluid, lat->nbm(), psi, W.lam[nxt], W.rbar[nxt],
                                W.lam[now], W.abar, g, lat->ph, odd, s);
@@ -640,6 +683,8 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
             launch_adj_rho(W.node_of, lat->nfluid, lat->nbm(), W.abar, W.nbar, g, W.rbar[now], s);
             cur = now;
         }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(lat->ev_rev[b], s));
     }
     launch_grad_scatter(lat->list(), lat->nbound, W.gacc, d_grad_xi, s);
     HIP_TRY(hipGetLastError());
@@ -680,6 +725,12 @@ mclbm_status mclbm_profile_read(mclbm_lattice* lat, double h_ms[3], int64_t h_la
 void mclbm_destroy(mclbm_lattice* lat) {
     if (!lat) return;
     drop_events(lat);
+    if (lat->aux) {
+        (void)hipStreamSynchronize(lat->aux);
+        for (hipEvent_t e : {lat->ev_start, lat->ev_rec[0], lat->ev_rec[1], lat->ev_rev[0], lat->ev_rev[1]})
+            if (e) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(lat->aux);
+    }
     delete lat;
 }
 
