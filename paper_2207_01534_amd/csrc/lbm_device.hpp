@@ -40,14 +40,23 @@ struct Geo {
 
 // Loads and stores at a 32-bit element offset from a wave-uniform base, so
 // that the compiler can address with a scalar base plus a 32-bit vector
-// offset instead of a 64-bit address per lane.
+// offset instead of a 64-bit address per lane.  That holds for elements of
+// at most 4 bytes (offsets < 2^30 elements: lattice indices, fluid ids);
+// wider elements (the float2 psi-hat and density fields, indexed by lattice
+// node) scale in 64 bits, since 8 * idx passes 2^32 beyond 2^29 nodes.
 template <class T>
 __device__ __forceinline__ T ld(const T* base, uint32_t i) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+    if constexpr (sizeof(T) > 4)
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)i * sizeof(T));
+    else
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
 }
 template <class T>
 __device__ __forceinline__ void st(T* base, uint32_t i, T v) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
+    if constexpr (sizeof(T) > 4)
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)i * sizeof(T)) = v;
+    else
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
 // The same at an element offset that may exceed 2^30 (scaled in 64 bits).

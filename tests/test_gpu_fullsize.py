@@ -1,0 +1,165 @@
+"""Parity at full size on sampled windows: the 512^3 sphere pack in the
+configuration the throughput benchmark times (populations sized to the fluid
+count, tau = (1.5, 0.6), G = 3.5), and a lattice of just under 2^30 nodes,
+the largest the library accepts (node indices past 2^29, where an 8-byte
+field's byte offset no longer fits in 32 bits).
+
+One step moves information by at most three nodes along each axis: f_i(x)
+at t+1 is the post-collision f_i of x - e_i, whose force reads psi-hat at
+x - e_i + e_k, and psi-hat at a solid node averages the densities of its
+fluid neighbours (Eqs. 1, 10-15); the force in the velocity readout reaches
+two nodes further.  So after k steps a window of the full lattice, stepped
+on its own by the FP64 oracle with periodic wrap, must agree with the full
+run everywhere more than 3k + 2 nodes inside its faces.  Windows sit at
+seeded positions, across the periodic wrap and at the highest node indices.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, OracleParams
+from paper_2207_01534_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 3
+WIN = 40
+MARGIN = 3 * STEPS + 2
+TAU, G = (1.5, 0.6), 3.5
+# (e_rho, e_u), field-max normalised.  FP32 velocity: the momentum is a sum of
+# 38 populations of size ~w rho, so its FP32 round-off is ~1e-7 absolute; at
+# t = 3 quiescent windows have |u| ~ 1e-3, which puts the normalised floor
+# near 1e-4, hence 2e-4.  FP16: the storage gate.
+BAR = {"f32": (1e-5, 2e-4), "f16": (2e-3, 2e-3)}
+
+
+def _index(starts, dims):
+    """Wrapped index vectors (z, y, x) of a WIN^3 window starting at starts (z, y, x)."""
+    return [(np.arange(WIN) + s) % d for s, d in zip(starts, dims)]
+
+
+def _take(a, idx, lead=0):
+    """Window of a numpy array or torch tensor whose last three axes are (z, y, x)."""
+    import torch
+    for ax, ix in enumerate(idx):
+        if isinstance(a, torch.Tensor):
+            a = torch.index_select(a, lead + ax, torch.as_tensor(ix, device=a.device))
+        else:
+            a = np.take(a, ix, axis=lead + ax)
+    return a.cpu().numpy() if isinstance(a, torch.Tensor) else a
+
+
+def _oracle_window(solid_w, xi_w, rho_w, g):
+    shape = (WIN, WIN, WIN)
+    o = Oracle(OracleParams(shape, tau=TAU, G=G, g=g), solid_w.astype(np.uint8),
+               np.asarray(xi_w, np.float32).astype(np.float64))
+    r = np.asarray(rho_w, np.float32).astype(np.float64)
+    r[:, solid_w != 0] = 0.0
+    o.init_equilibrium(r)
+    o.run(STEPS)
+    rho, _, _, u = o.fields()
+    return rho, u
+
+
+def _errors(rho_g, u_g, rho_o, u_o, solid_w):
+    c = slice(MARGIN, WIN - MARGIN)
+    fl = solid_w[c, c, c] == 0
+    rg, ro = rho_g[:, c, c, c], rho_o[:, c, c, c]
+    ug, uo = u_g[:, c, c, c], u_o[:, c, c, c]
+    e_rho = max(np.abs(rg[s][fl] - ro[s][fl]).max() / np.abs(ro[s][fl]).max() for s in range(2))
+    un = np.sqrt((uo ** 2).sum(0))[fl].max()
+    e_u = np.sqrt(((ug - uo) ** 2).sum(0))[fl].max() / un
+    return e_rho, e_u, un, int(fl.sum())
+
+
+def _check_windows(lat, solid, xi, rho, g, windows, storage, label):
+    import torch
+    torch.cuda.synchronize()
+    rho_full = lat.density()
+    u_full = lat.velocity()
+    dims = tuple(solid.shape)
+    for starts in windows:
+        idx = _index(starts, dims)
+        solid_w = _take(solid, idx).astype(np.uint8)
+        e_rho, e_u, un, nfl = _errors(_take(rho_full, idx, 1).astype(np.float64),
+                                      _take(u_full, idx, 1).astype(np.float64),
+                                      *_oracle_window(solid_w, _take(xi, idx), _take(rho, idx, 1), g), solid_w)
+        print(f"[window] {label} {storage} start(z,y,x)={starts} fluid={nfl} e_rho={e_rho:.2e} "
+              f"e_u={e_u:.2e} u_max={un:.2e}", flush=True)
+        assert nfl > 100
+        assert e_rho <= BAR[storage][0] and e_u <= BAR[storage][1], (starts, e_rho, e_u)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_spheres512_bench_configuration_windows(storage):
+    import torch
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams, Storage
+    w = wl.workload("spheres512")
+    print(f"[case] spheres512 {w.shape} storage={storage} steps={STEPS}", flush=True)
+    st = {"f32": Storage.F32, "f16": Storage.F16}[storage]
+    p = LatticeParams(shape=w.shape, tau=w.tau, G=w.G, g=w.g, storage=st, fluid_capacity=w.n_fluid)
+    assert tuple(w.tau) == TAU and w.G == G
+    rho = w.rho.astype(np.float32)
+    lat = Lattice(p, torch.as_tensor(w.solid), torch.as_tensor(w.xi), torch.as_tensor(rho))
+    lat.step(STEPS)
+    rng = np.random.default_rng(5121)
+    dims = w.solid.shape
+    windows = [tuple(int(rng.integers(0, d)) for d in dims) for _ in range(3)]
+    windows += [(dims[0] - 20, dims[1] - 20, dims[2] - 20)]   # across the wrap, highest indices
+    _check_windows(lat, w.solid, w.xi, rho, w.g, windows, storage, "spheres512")
+    d = lat.diagnostics()
+    assert d["nonfinite"] == 0 and d["n_fluid"] == w.n_fluid
+    del lat
+    torch.cuda.empty_cache()
+
+
+def _max_lattice(device):
+    """1024 x 1024 x 1022 nodes (just under 2^30): a smooth pseudo-random solid
+    field thresholded to about 30 % porosity, xi ~ U[-0.4, 0.4] at solid
+    voxels, and two components separated by tanh interfaces (W = 5) along a
+    second smooth field.  Built on the device in z slabs."""
+    import torch
+    nx, ny, nz = 1024, 1024, 1022
+    gen = torch.Generator(device=device).manual_seed(1030)
+    k = torch.rand((3, 3), generator=gen, device=device) * 0.15 + 0.08   # wave numbers
+    ph = torch.rand((3, 3), generator=gen, device=device) * 6.283
+    x = torch.arange(nx, device=device, dtype=torch.float32)
+    y = torch.arange(ny, device=device, dtype=torch.float32)
+    solid = torch.empty((nz, ny, nx), dtype=torch.uint8, device=device)
+    rho = torch.empty((2, nz, ny, nx), dtype=torch.float32, device=device)
+    for z0 in range(0, nz, 64):
+        z = torch.arange(z0, min(z0 + 64, nz), device=device, dtype=torch.float32)[:, None, None]
+        Z, Y, X = z, y[None, :, None], x[None, None, :]
+        s = (torch.sin(k[0, 0] * X + ph[0, 0] + 1.3 * torch.sin(k[0, 1] * Y + ph[0, 1]))
+             + torch.sin(k[1, 0] * Y + ph[1, 0] + 0.9 * torch.sin(k[1, 1] * Z + ph[1, 1]))
+             + torch.sin(k[2, 0] * Z + ph[2, 0] + 1.1 * torch.sin(k[2, 1] * X + ph[2, 1])))
+        solid[z0:z0 + z.shape[0]] = (s < 0.55).to(torch.uint8)
+        q = torch.sin(0.05 * X + 0.3) * torch.sin(0.043 * Y + 1.1) * torch.sin(0.047 * Z + 2.0)
+        phi = 0.5 * (1.0 + torch.tanh(q * 12.0 / 2.5))
+        rho[0, z0:z0 + z.shape[0]] = 0.03 + 0.97 * phi
+        rho[1, z0:z0 + z.shape[0]] = 0.03 + 0.97 * (1.0 - phi)
+    xi = (torch.rand((nz, ny, nx), generator=gen, device=device) * 0.8 - 0.4) * solid
+    return (nx, ny, nz), solid, xi, rho
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_max_size_lattice_windows(storage):
+    import torch
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams, Storage
+    shape, solid, xi, rho = _max_lattice("cuda")
+    n = shape[0] * shape[1] * shape[2]
+    assert 2 ** 29 < n < 2 ** 30 - 512
+    n_fluid = int(n - int(solid.sum(dtype=torch.int64)))
+    print(f"[case] max lattice {shape} n={n} fluid={n_fluid} storage={storage} steps={STEPS}", flush=True)
+    st = {"f32": Storage.F32, "f16": Storage.F16}[storage]
+    p = LatticeParams(shape=shape, tau=TAU, G=G, storage=st, fluid_capacity=n_fluid)
+    lat = Lattice(p, solid, xi, rho)
+    assert lat.fluid_count() == n_fluid
+    lat.step(STEPS)
+    dims = tuple(solid.shape)
+    windows = [(dims[0] - WIN + 4, dims[1] - WIN + 2, dims[2] - WIN + 1),   # highest node indices
+               (dims[0] - 12, dims[1] - 25, dims[2] - 9),                     # across the wrap
+               (600, 3, 517)]
+    g0 = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    _check_windows(lat, solid, xi, rho, g0, windows, storage, "max")
+    del lat
+    torch.cuda.empty_cache()
