@@ -69,6 +69,23 @@ __device__ __forceinline__ void st_far(T* base, uint32_t i, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)i * sizeof(T)) = v;
 }
 
+// Population slots at an element offset scaled in 32 bits (NARROW: the
+// caller guarantees offset * sizeof(T) < 2^32) or in 64 bits (WIDE).
+template <bool WIDE, class T>
+__device__ __forceinline__ T ld_pop(const T* base, uint32_t i) {
+    if constexpr (WIDE)
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)i * sizeof(T));
+    else
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <bool WIDE, class T>
+__device__ __forceinline__ void st_pop(T* base, uint32_t i, T v) {
+    if constexpr (WIDE)
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)i * sizeof(T)) = v;
+    else
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
 // Node index and periodic neighbour offsets of one node.
 struct Nb {
     uint32_t idx;
@@ -139,22 +156,42 @@ __device__ __forceinline__ float inv_total(float2 r) {
     return t > 0.0f ? 1.0f / t : 0.0f;
 }
 
-// Population storage: 36 moving planes of T (component-major, directions
-// 1..18) and 2 FP32 rest planes, each plane np elements long and indexed by
-// fluid id.
+// One population of both components (same direction, same slot), stored
+// next to each other so that one load or store moves both.
+template <class T>
+struct alignas(2 * sizeof(T)) Pair {
+    T v[2];
+};
+
+// Population storage: 18 moving planes (directions 1..18) of component pairs
+// in the codec's type, and one plane of FP32 rest-population pairs; each plane
+// is np slots long and indexed by fluid id.
 template <class C>
 struct Pops {
     typename C::T* mv;
     float* rest;
-    __device__ __forceinline__ typename C::T* plane(int s, int i, int np) const {
-        return mv + (size_t)(s * (Q - 1) + (i - 1)) * (size_t)np;
+    using P2 = Pair<typename C::T>;
+    __device__ __forceinline__ P2* plane(int i, int np) const {
+        return reinterpret_cast<P2*>(mv) + (size_t)(i - 1) * (size_t)np;
     }
+    __device__ __forceinline__ Pair<float>* rests() const { return reinterpret_cast<Pair<float>*>(rest); }
+    // component s of direction i at slot k
+    __device__ __forceinline__ typename C::T* at(int s, int i, uint32_t k, int np) const {
+        return plane(i, np)[k].v + s;
+    }
+    __device__ __forceinline__ float* rest_at(int s, uint32_t k) const { return rests()[k].v + s; }
 };
+
+// Slot offsets reach 2 np pairs (odd steps address a pair of planes from the
+// lower one) of at most 8 bytes: 32-bit byte offsets hold while 16 np < 2^32.
+inline bool pops_wide(int np) { return (uint64_t)16 * (uint64_t)np >= (1ull << 32); }
 
 // ---------------------------------------------------------------------------
 // Tile-sparse AA-pattern streaming with halfway bounce-back.
-// Only fluid nodes own populations: fluid node k (its fluid id) owns slots
-// (i, k) of the 38 planes.  The state at an even time level keeps f_i(x) in
+// Only fluid nodes own populations: fluid node k (its fluid id) owns slot
+// (i, k) of each direction plane, which holds f_i of both components side by
+// side, so every slot access moves the two components in one load or store.
+// The state at an even time level keeps f_i(x) in
 // slot (i, k(x)); at an odd level f_i(x) sits in slot (opp i, k(x - e_i)) if
 // x - e_i is fluid and in (i, k(x)) otherwise (the bounced population).
 //   even step at fluid x: read slots (i, k); write f*_i(x) to (opp i, k);
@@ -177,15 +214,17 @@ struct RawNode {
 };
 
 // Issue the loads of fluid node k's incoming populations (no decoding).
-template <class C, bool ODD, class FidAt>
+template <class C, bool ODD, bool WIDE, class FidAt>
 __device__ __forceinline__ void load_raw(RawNode<C>& r, const Pops<C>& P, uint32_t k, FidAt fid_at, int np) {
-    r.rest[0] = ld(P.rest, k);
-    r.rest[1] = ld(P.rest + np, k);
+    const Pair<float> rp = ld_pop<WIDE>(P.rests(), k);
+    r.rest[0] = rp.v[0];
+    r.rest[1] = rp.v[1];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if constexpr (!ODD) {
-            r.h[0][i] = ld(P.plane(0, i, np), k);
-            r.h[1][i] = ld(P.plane(1, i, np), k);
+            const typename Pops<C>::P2 p = ld_pop<WIDE>(P.plane(i, np), k);
+            r.h[0][i] = p.v[0];
+            r.h[1][i] = p.v[1];
         } else {
             // slot (opp i, src) or, across a wall, (i, k); directions 2k-1, 2k
             // have adjacent planes, so both are one offset from the lower one
@@ -193,8 +232,9 @@ __device__ __forceinline__ void load_raw(RawNode<C>& r, const Pops<C>& P, uint32
             const bool wall = src < 0;
             const int lo = (i & 1) ? i : i - 1;
             const uint32_t e = wall ? k + ((i & 1) ? 0u : (uint32_t)np) : (uint32_t)src + ((i & 1) ? (uint32_t)np : 0u);
-            r.h[0][i] = ld_far(P.plane(0, lo, np), e);
-            r.h[1][i] = ld_far(P.plane(1, lo, np), e);
+            const typename Pops<C>::P2 p = ld_pop<WIDE>(P.plane(lo, np), e);
+            r.h[0][i] = p.v[0];
+            r.h[1][i] = p.v[1];
         }
     }
 }
@@ -227,7 +267,7 @@ template <class C, bool ODD, class FidAt>
 __device__ __forceinline__ void load_node(float (&f)[2][Q], const Pops<C>& P, const float2* rprev,
                                           uint32_t nbm, const Nb& nb, uint32_t k, FidAt fid_at, int np) {
     RawNode<C> r;
-    load_raw<C, ODD>(r, P, k, fid_at, np);
+    load_raw<C, ODD, true>(r, P, k, fid_at, np);
     decode_node<C>(f, r, nbm, [&](int i, bool solid) { return ld(rprev, solid ? nb.idx : nb.at(i, -1)); });
 }
 
@@ -250,7 +290,7 @@ __device__ __forceinline__ float sum19(const float (&f)[Q]) {
 // populations is absorbed by the FP32 rest population.
 // mass: incoming component densities; rho_ref: this node's density as the
 // decoder will read it next step (F16/BF16 codecs only).
-template <class C, bool ODD, class FidAt>
+template <class C, bool ODD, bool WIDE, class FidAt>
 __device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C>& D, const float (&mass)[2],
                                            float2 rho_ref, uint32_t k, FidAt fid_at, int np) {
     float sum0 = 0.0f, sum1 = 0.0f;
@@ -260,23 +300,21 @@ __device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C
     for (int i = 1; i < Q; ++i) {
         const typename C::T h0 = C::enc(fs[0][i], weight(i), rho_ref.x, inv_t);
         const typename C::T h1 = C::enc(fs[1][i], weight(i), rho_ref.y, inv_t);
+        const typename Pops<C>::P2 hp{{h0, h1}};
         if constexpr (!ODD) {
-            st(D.plane(0, opp(i), np), k, h0);
-            st(D.plane(1, opp(i), np), k, h1);
+            st_pop<WIDE>(D.plane(opp(i), np), k, hp);
         } else {
             // slot (i, dst) or, across a wall, (opp i, k), from the pair's lower plane
             const int dst = fid_at(i, +1);
             const bool wall = dst < 0;
             const int lo = (i & 1) ? i : i - 1;
             const uint32_t e = wall ? k + ((i & 1) ? (uint32_t)np : 0u) : (uint32_t)dst + ((i & 1) ? 0u : (uint32_t)np);
-            st_far(D.plane(0, lo, np), e, h0);
-            st_far(D.plane(1, lo, np), e, h1);
+            st_pop<WIDE>(D.plane(lo, np), e, hp);
         }
         sum0 += C::dec(h0, weight(i), rho_ref.x, rt);
         sum1 += C::dec(h1, weight(i), rho_ref.y, rt);
     }
-    st(D.rest, k, mass[0] - sum0);
-    st(D.rest + np, k, mass[1] - sum1);
+    st_pop<WIDE>(D.rests(), k, Pair<float>{{mass[0] - sum0, mass[1] - sum1}});
 }
 
 // Physical parameters in FP32.

@@ -202,12 +202,10 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* _
             sum0 += C::dec(h0, weight(i), 0.f, 0.f);
             sum1 += C::dec(h1, weight(i), 0.f, 0.f);
         }
-        st(P.plane(0, i, g.np), k, h0);
-        st(P.plane(1, i, g.np), k, h1);
+        st_pop<true>(P.plane(i, g.np), k, typename Pops<C>::P2{{h0, h1}});
     }
     // rest population from the node mass (see store_node)
-    st(P.rest, k, r0 - sum0);
-    st(P.rest + g.np, k, r1 - sum1);
+    st_pop<true>(P.rests(), k, Pair<float>{{r0 - sum0, r1 - sum1}});
 }
 
 // ---------------------------------------------------------------------------
@@ -288,7 +286,7 @@ struct HaloFid {
 // staged as an LDS halo as well, while the thread's first node is loaded.
 // At least 8 waves per SIMD in even steps (7 with a decoding halo) and 6
 // in odd steps; the compiler's default schedule would hold ~105 VGPRs.
-template <class C, bool ODD>
+template <class C, bool ODD, bool WIDE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 6 : (C::kRef ? 7 : 8))))
 void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
                float2* __restrict__ psi, Geo g) {
@@ -307,7 +305,7 @@ void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const floa
     auto fetch = [&](int j, RawNode<C>& r, TilePos& q) {
         const uint32_t k = (uint32_t)(base + j);
         q = TilePos(S.loc[k]);
-        load_raw<C, ODD>(r, P, k, HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1}, g.np);
+        load_raw<C, ODD, WIDE>(r, P, k, HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1}, g.np);
     };
     auto finish = [&](const RawNode<C>& r, const TilePos& q) {
         const uint32_t idx = (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)));
@@ -382,7 +380,7 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
 // (3 waves per SIMD), too few waves to hide the memory latency of the
 // population traffic.  Even steps fit 5 waves per SIMD without spilling; odd
 // steps (gathers through the fluid-id halo) are held to 4.
-template <class C, bool ODD>
+template <class C, bool ODD, bool WIDE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 5))) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
                                                        const uint32_t* __restrict__ nbm,
                                                        const float2* __restrict__ rprev,
@@ -404,7 +402,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 5)
         const uint32_t k = (uint32_t)(base + j);
         const TilePos q(S.loc[k]);
         h = HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1};
-        load_raw<C, ODD>(r, P, k, h, g.np);
+        load_raw<C, ODD, WIDE>(r, P, k, h, g.np);
     };
     auto finish = [&](int j, const RawNode<C>& r, const HaloFid& h) {
         const uint32_t k = (uint32_t)(base + j);
@@ -421,7 +419,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 5)
         total_force(rho, acc, ph, F);
         float u[3];
         collide(f, rho, F, ph, u);
-        store_node<C, ODD>(f, D, rho, psit[h.tz][h.ty][h.tx], k, h, g.np);
+        store_node<C, ODD, WIDE>(f, D, rho, psit[h.tz][h.ty][h.tx], k, h, g.np);
     };
     const int j0 = threadIdx.x;
     RawNode<C> r;
@@ -599,16 +597,24 @@ void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const fl
     hipLaunchKernelGGL(k_init<C>, row_grid(g), dim3(64), 0, s, P, nbm, fid, rho, rprev, g);
 }
 
+template <class C, bool ODD, bool WIDE>
+static void launch_density_as(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev,
+                              float2* psi, const Geo& g, hipStream_t s) {
+    hipLaunchKernelGGL((k_density<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, nbm, rprev, psi,
+                       g);
+}
+
 template <class C>
 void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
                     const Geo& g, int odd, hipStream_t s) {
     if (S.nactive <= 0) return;
+    const bool wide = pops_wide(g.np);
     if (odd)
-        hipLaunchKernelGGL((k_density<C, true>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, nbm, rprev,
-                           psi, g);
+        wide ? launch_density_as<C, true, true>(P, S, nbm, rprev, psi, g, s)
+             : launch_density_as<C, true, false>(P, S, nbm, rprev, psi, g, s);
     else
-        hipLaunchKernelGGL((k_density<C, false>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, nbm, rprev,
-                           psi, g);
+        wide ? launch_density_as<C, false, true>(P, S, nbm, rprev, psi, g, s)
+             : launch_density_as<C, false, false>(P, S, nbm, rprev, psi, g, s);
 }
 
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
@@ -618,17 +624,25 @@ void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* n
                        g);
 }
 
+template <class C, bool ODD, bool WIDE>
+static void launch_collide_as(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
+                              const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, hipStream_t s) {
+    hipLaunchKernelGGL((k_collide_stream<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, nbm,
+                       rprev, psi, g, ph);
+}
+
 template <class C>
 void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
                            const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, int odd,
                            hipStream_t s) {
     if (S.nactive <= 0) return;
+    const bool wide = pops_wide(g.np);
     if (odd)
-        hipLaunchKernelGGL((k_collide_stream<C, true>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, nbm,
-                           rprev, psi, g, ph);
+        wide ? launch_collide_as<C, true, true>(P, D, S, nbm, rprev, psi, g, ph, s)
+             : launch_collide_as<C, true, false>(P, D, S, nbm, rprev, psi, g, ph, s);
     else
-        hipLaunchKernelGGL((k_collide_stream<C, false>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, nbm,
-                           rprev, psi, g, ph);
+        wide ? launch_collide_as<C, false, true>(P, D, S, nbm, rprev, psi, g, ph, s)
+             : launch_collide_as<C, false, false>(P, D, S, nbm, rprev, psi, g, ph, s);
 }
 
 int fields_blocks(const Geo& g) {

@@ -53,7 +53,7 @@ __device__ __forceinline__ OpenSlot slot_of(int i, bool odd, uint32_t k, uint32_
 template <class C>
 __device__ __forceinline__ float read_pop(const Pops<C>& P, int s, const OpenSlot& q, int i, const float2* psi,
                                           int np) {
-    const typename C::T h = ld(P.plane(s, q.dir, np), q.id);
+    const typename C::T h = *P.at(s, q.dir, q.id, np);
     if constexpr (C::kRef) {
         const float2 r = ld(psi, q.writer);
         return C::dec(h, weight(i), s ? r.y : r.x, r.x + r.y);
@@ -74,7 +74,7 @@ __device__ __forceinline__ float write_pop(const Pops<C>& P, int s, const OpenSl
         inv = inv_total(r);
     }
     const typename C::T h = C::enc(v, weight(i), rw, inv);
-    st(P.plane(s, q.dir, np), q.id, h);
+    *P.at(s, q.dir, q.id, np) = h;
     return C::dec(h, weight(i), rw, rt);
 }
 
@@ -117,7 +117,7 @@ __global__ void k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const uin
     float ff[2][Q];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        ff[s][0] = ld(P.rest + (size_t)s * np, kf);
+        ff[s][0] = *P.rest_at(s, kf);
 #pragma unroll
         for (int i = 1; i < Q; ++i) ff[s][i] = read_pop<C>(P, s, slot_of(i, odd, kf, mf, nf, fid), i, psi, np);
     }
@@ -145,7 +145,7 @@ __global__ void k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const uin
         const float v = ff[imposed][i] + feq(i, rho_b, u, usq) - feq(i, rf[imposed], u, usq);
         moving += write_pop<C>(P, imposed, slot_of(i, odd, kb, mb, nb, fid), i, v, psi, np);
     }
-    st(P.rest + (size_t)imposed * np, kb, rho_b - moving);  // exact imposed density
+    *P.rest_at(imposed, kb) = rho_b - moving;  // exact imposed density
 #pragma unroll
     for (int i = 1; i < Q; ++i)
         if (DX[i] == dir_in) {
@@ -164,7 +164,7 @@ __global__ void k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const uin
         float sum = 0.f;
 #pragma unroll
         for (int i = 1; i < Q; ++i) sum += write_pop<C>(P, s, slot_of(i, odd, kg, mg, ng, fid), i, weight(i) * r, psi, np);
-        st(P.rest + (size_t)s * np, kg, r - sum);
+        *P.rest_at(s, kg) = r - sum;
     }
 }
 
