@@ -192,6 +192,30 @@ def calibrate_copy():
     print(json.dumps({"calibration": "copy", "bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}))
 
 
+def copy_bandwidth(reps=10):
+    """Achievable HBM bandwidth on this GPU: a plain elementwise copy, 1 GiB read
+    + 1 GiB written per launch (far beyond the last-level cache), timed with
+    HIP events on the current stream; GB/s of the median launch."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        torch.neg(a, out=b)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.neg(a, out=b)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    times.sort()
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / times[reps // 2] / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +273,8 @@ def main():
 
     k2 = main_res["collide_stream_gbs"]
     name = w.name if not args.shape else None
+    copy_gbs = copy_bandwidth()
+    _log(f"plain copy: {copy_gbs:.0f} GB/s")
 
     def traffic_of(res, storage):
         t = measured_traffic(name, storage)
@@ -276,7 +302,10 @@ def main():
                      "traffic": round(traffic) if traffic else None,
                      "traffic_gbs": traffic_gbs,
                      "kernel": "k_collide_stream",
-                     "algorithmic_bytes_per_launch": main_res["collide_stream_bytes_per_launch"]},
+                     "algorithmic_bytes_per_launch": main_res["collide_stream_bytes_per_launch"],
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(k2 / copy_gbs, 4),
+                     "traffic_frac_of_copy": round(traffic_gbs / copy_gbs, 4) if traffic_gbs else None},
         "cpu_baseline": cpu,
         "mflups": round(main_res["mflups"], 1),
         "gbs_alg_step": round(main_res["gbs_alg_step"], 1),

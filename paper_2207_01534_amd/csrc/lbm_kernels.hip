@@ -378,10 +378,12 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
 // a separate slot.
 // Register budgets: the compiler's default schedule holds up to ~140 VGPRs
 // (3 waves per SIMD), too few waves to hide the memory latency of the
-// population traffic.  Even steps fit 5 waves per SIMD without spilling; odd
-// steps (gathers through the fluid-id halo) are held to 4.
+// population traffic.  FP32 runs 4 waves per SIMD (up to 128 VGPRs; no
+// spill with 32-bit slot offsets); the FP16/BF16 codecs, whose populations
+// take half the registers, run 5 (odd steps spill a few dwords, which costs
+// less than the lost wave).
 template <class C, bool ODD, bool WIDE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 5))) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 : 4))) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
                                                        const uint32_t* __restrict__ nbm,
                                                        const float2* __restrict__ rprev,
                                                        const float2* __restrict__ psi, Geo g, Phys ph) {
