@@ -59,16 +59,6 @@ __device__ __forceinline__ void st(T* base, uint32_t i, T v) {
         *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
-// The same at an element offset that may exceed 2^30 (scaled in 64 bits).
-template <class T>
-__device__ __forceinline__ T ld_far(const T* base, uint32_t i) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)i * sizeof(T));
-}
-template <class T>
-__device__ __forceinline__ void st_far(T* base, uint32_t i, T v) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)i * sizeof(T)) = v;
-}
-
 // Population slots at an element offset scaled in 32 bits (NARROW: the
 // caller guarantees offset * sizeof(T) < 2^32) or in 64 bits (WIDE).
 template <bool WIDE, class T>

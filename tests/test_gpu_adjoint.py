@@ -85,9 +85,14 @@ def test_small_gradient_against_oracle_fd(steps, every):
     # directional derivative along a random direction over all boundary voxels
     v = np.where(bs, rng.standard_normal(bs.shape), 0.0)
     v /= np.abs(v).max()
-    dd = (_oracle_loss(shape, solid, xi64 + eps * v, rho, tau, G, g, steps, region)
-          - _oracle_loss(shape, solid, xi64 - eps * v, rho, tau, G, g, steps, region)) / (2 * eps)
-    assert float((grad * v).sum()) == pytest.approx(dd, rel=1e-3, abs=1e-3 * scale)
+    def directional(e):
+        return (_oracle_loss(shape, solid, xi64 + e * v, rho, tau, G, g, steps, region)
+                - _oracle_loss(shape, solid, xi64 - e * v, rho, tau, G, g, steps, region)) / (2 * e)
+    dd, dd_half = directional(eps), directional(eps / 2)
+    # the finite difference itself is converged: halving the step changes it
+    # by the O(eps^2) truncation term only
+    assert dd_half == pytest.approx(dd, rel=1e-5, abs=1e-6 * scale)
+    assert float((grad * v).sum()) == pytest.approx(dd_half, rel=1e-3, abs=1e-3 * scale)
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden finite differences not generated")
