@@ -586,13 +586,26 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
 
 // The reverse sweep's auxiliary stream and events, created on first use on
 // the lattice's device and kept until mclbm_destroy.
+// All or nothing: on a failure the lattice keeps no partial set.
 static hipError_t ensure_aux(mclbm_lattice* lat) {
     if (lat->aux) return hipSuccess;
-    hipError_t e = hipStreamCreateWithFlags(&lat->aux, hipStreamNonBlocking);
-    hipEvent_t* evs[5] = {&lat->ev_start, &lat->ev_rec[0], &lat->ev_rec[1], &lat->ev_rev[0], &lat->ev_rev[1]};
-    for (hipEvent_t* p : evs)
-        if (e == hipSuccess) e = hipEventCreateWithFlags(p, hipEventDisableTiming);
-    return e;
+    hipStream_t st = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (st) (void)hipStreamDestroy(st);
+        return e;
+    }
+    lat->aux = st;
+    lat->ev_start = ev[0];
+    lat->ev_rec[0] = ev[1];
+    lat->ev_rec[1] = ev[2];
+    lat->ev_rev[0] = ev[3];
+    lat->ev_rev[1] = ev[4];
+    return hipSuccess;
 }
 
 mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
@@ -634,6 +647,15 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
     hipStream_t s2 = lat->aux;
     HIP_TRY(hipEventRecord(lat->ev_start, s));
     HIP_TRY(hipStreamWaitEvent(s2, lat->ev_start, 0));
+    // on every way out, later work on the lattice's stream also waits for
+    // whatever was queued on the auxiliary stream (already implied on success)
+    struct JoinAux {
+        hipStream_t s, s2;
+        hipEvent_t e;
+        ~JoinAux() {
+            if (hipEventRecord(e, s2) == hipSuccess) (void)hipStreamWaitEvent(s, e, 0);
+        }
+    } join{s, s2, lat->ev_start};
     auto recompute = [&](int seg) -> mclbm_status {
         const int b = seg & 1;
         const int64_t ta = t0 + (int64_t)seg * every;
