@@ -117,3 +117,28 @@ def test_adjoint64_full_against_golden_fd():
     for v, a in zip(rec["voxels"], adj):
         print(f"   {v['zyx']} fd={v['fd']:.6e} adj={a:.6e}", flush=True)
     assert err <= 1e-3
+
+
+def test_adjoint_entry_points_refuse_unsupported_lattices():
+    """The adjoint covers FP32 storage with periodic x: FP16 storage and open
+    planes are refused with an error, and the lattice stays usable."""
+    import torch
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams, MclbmError, Storage
+    shape = (12, 10, 8)
+    nx, ny, nz = shape
+    solid = wl.random_mask(shape, 0.25, seed=77)
+    xi = wl.uniform_xi(solid, -0.4, 0.4, seed=78)
+    rho = wl.tanh_droplet(shape, 3.0)
+    rho[:, solid != 0] = 0
+    half = Lattice(LatticeParams(shape=shape, storage=Storage.F16), torch.as_tensor(solid), torch.as_tensor(xi),
+                   torch.as_tensor(rho.astype(np.float32)))
+    with pytest.raises(MclbmError):
+        half.step_checkpointed(4, 2)
+    half.step(2)
+    opened = Lattice(LatticeParams(shape=(nx + 2, ny, nz)), torch.zeros((nz, ny, nx + 2), dtype=torch.uint8),
+                     None, torch.full((2, nz, ny, nx + 2), 0.5))
+    opened.set_open_x(0.52, 0.5)
+    with pytest.raises(MclbmError):
+        opened.step_checkpointed(4, 2)
+    opened.step(2)
+    assert opened.time == 2

@@ -62,7 +62,8 @@ def _oracle_fields(o):
     return r, u, F, o.pressure()
 
 
-@pytest.mark.parametrize("storage,e_rho_bar,e_u_bar", [(0, 1e-5, 1e-4), (1, 2e-3, 2e-3)], ids=["f32", "f16"])
+@pytest.mark.parametrize("storage,e_rho_bar,e_u_bar", [(0, 1e-5, 1e-4), (1, 2e-3, 2e-3), (2, 2e-2, 2e-2)],
+                         ids=["f32", "f16", "bf16"])
 def test_open_planes_match_oracle_with_inlet_ramp(storage, e_rho_bar, e_u_bar):
     gshape, gsolid, gxi, grho, oshape, osolid, oxi, orho = _case()
     print(f"[case] open planes {oshape} (+2 ghost planes) storage={storage}", flush=True)
