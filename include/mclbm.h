@@ -206,6 +206,13 @@ mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src);
 /* L at the current time level; synchronises the stream. */
 mclbm_status mclbm_loss_snw(mclbm_lattice* lat, const uint8_t* d_region, double* h_L);
 
+/* Outlet flux of component 1 through a region (the alternative loss of the
+ * adjoint): L = sum over the fluid voxels x of d_region of rho1(x) u_x(x),
+ * with rho1 from Eq. 3 and u the common velocity of Eq. 8 including the
+ * half-force shift (Eqs. 10-15 at the current time level).  d_region:
+ * uint8[N] (nonzero = in the region).  FP64 sum; synchronises the stream. */
+mclbm_status mclbm_loss_flux(mclbm_lattice* lat, const uint8_t* d_region, double* h_L);
+
 /* Bytes of the checkpoint buffer for nsteps steps saved every `every`
  * steps: ceil(nsteps/every) population states. */
 mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes);
@@ -236,6 +243,14 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
  * stream reaches the end of the call's work. */
 mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
                                 const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi);
+
+/* The same reverse sweep for the outlet flux of mclbm_loss_flux (same
+ * arguments, work buffer and output).  The flux depends on the forces at
+ * the final time, so its seed includes the adjoint of the pseudopotential
+ * sums there: xi receives a direct term through the final virtual solid
+ * densities (Eqs. 14-15) besides the one carried back through the steps. */
+mclbm_status mclbm_gradient_flux(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
+                                 const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi);
 
 /* Per-kernel timing of mclbm_step with HIP events recorded on the lattice's
  * stream around each launch (measurement support; two event records per

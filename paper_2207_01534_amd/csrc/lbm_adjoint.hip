@@ -92,6 +92,127 @@ __global__ void k_loss_final(const double* __restrict__ partial, int nblocks, do
 }
 
 // ---------------------------------------------------------------------------
+// Outlet flux L = sum_{fluid x in R} rho1 u_x with the common velocity of
+// Eq. 8 (half-force shift included): FP64 partials of (L, |R|).  psi holds
+// psi-hat of the same time level (its forces enter u).
+// ---------------------------------------------------------------------------
+// Local quantities of the flux loss at one fluid node.
+struct FluxNode {
+    float rho[2], A[2][3], u[3], rt;
+};
+
+template <bool ODD>
+__device__ __forceinline__ FluxNode flux_node(const Pops<CF>& P, const int* fid, const float2* psi, uint32_t m,
+                                              const Nb& nb, const Geo& g, const Phys& ph) {
+    FluxNode q;
+    float f[2][Q];
+    load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx], [&](int i, int s) { return fid[nb.at(i, s)]; },
+                       g.np);
+    q.rho[0] = sum19(f[0]);
+    q.rho[1] = sum19(f[1]);
+    psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, q.A);
+    float F[2][3];
+    total_force(q.rho, q.A, ph, F);
+    float j[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            j[0] += DX[i] * f[s][i];
+            j[1] += DY[i] * f[s][i];
+            j[2] += DZ[i] * f[s][i];
+        }
+    q.rt = q.rho[0] + q.rho[1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.u[a] = (j[a] + 0.5f * (F[0][a] + F[1][a])) / q.rt;
+    return q;
+}
+
+template <bool ODD>
+__global__ __launch_bounds__(256) void k_loss_flux_partial(Pops<CF> P, const int* __restrict__ fid,
+                                                           const uint32_t* __restrict__ nbm,
+                                                           const uint8_t* __restrict__ region,
+                                                           const float2* __restrict__ psi, Geo g, Phys ph,
+                                                           double* __restrict__ partial) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double v = 0.0, c = 0.0;
+    if (x < g.nx && y < g.ny) {
+        const Nb nb(x, y, z, g);
+        const uint32_t m = nbm[nb.idx];
+        if (!(m & SELF_SOLID) && region[nb.idx]) {
+            const FluxNode q = flux_node<ODD>(P, fid, psi, m, nb, g, ph);
+            v = (double)q.rho[0] * (double)q.u[0];
+            c = 1.0;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        v += __shfl_xor(v, off);
+        c += __shfl_xor(c, off);
+    }
+    __shared__ double red[4][2];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    if ((tid & 63) == 0) {
+        red[tid >> 6][0] = v;
+        red[tid >> 6][1] = c;
+    }
+    __syncthreads();
+    if (tid < 2) {
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) s += red[w][tid];
+        const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        partial[(size_t)b * 2 + tid] = s;
+    }
+}
+
+// Seed of the flux loss at the final time.  With u_x = (j_x + (F1_x + F2_x)/2)
+// / rho and F^s = -G rho^s A^(other) + rho^s g^s, holding A fixed:
+//   dL/drho1 = u_x + rho1 ((g1_x - G A2_x)/2 - u_x) / rho,
+//   dL/drho2 = rho1 ((g2_x - G A1_x)/2 - u_x) / rho,   dL/dj_x = rho1 / rho,
+//   dL/dA1_x = -G rho1 rho2 / (2 rho),               dL/dA2_x = -G rho1^2 / (2 rho);
+// so lambda_loc_i^s = dL/drho^s + e_ix rho1/rho, and Abar carries the A terms
+// (planes 0..2: A of component 1, 3..5: A of component 2) to the IVSD and
+// density adjoints, which return the neighbours' share and the direct xi term.
+template <bool ODD>
+__global__ __launch_bounds__(256) void k_adj_seed_flux(Pops<CF> P, const int* __restrict__ fid,
+                                                       const uint32_t* __restrict__ nbm,
+                                                       const uint8_t* __restrict__ region,
+                                                       const float2* __restrict__ psi, Geo g, Phys ph,
+                                                       float* __restrict__ lam, float* __restrict__ abar) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const Nb nb(x, y, z, g);
+    const size_t n = (size_t)g.n;
+    const uint32_t m = nbm[nb.idx];
+    float l0 = 0.f, l1 = 0.f, lj = 0.f, a1 = 0.f, a2 = 0.f;
+    if (!(m & SELF_SOLID) && region[nb.idx]) {
+        const FluxNode q = flux_node<ODD>(P, fid, psi, m, nb, g, ph);
+        const float inv = 1.0f / q.rt;
+        l0 = q.u[0] + q.rho[0] * (0.5f * (ph.g[0][0] - ph.G * q.A[1][0]) - q.u[0]) * inv;
+        l1 = q.rho[0] * (0.5f * (ph.g[1][0] - ph.G * q.A[0][0]) - q.u[0]) * inv;
+        lj = q.rho[0] * inv;
+        a1 = -0.5f * ph.G * q.rho[0] * q.rho[1] * inv;
+        a2 = -0.5f * ph.G * q.rho[0] * q.rho[0] * inv;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        lam[(size_t)i * n + nb.idx] = l0 + DX[i] * lj;
+        lam[(size_t)(Q + i) * n + nb.idx] = l1 + DX[i] * lj;
+    }
+    if (!(m & SELF_SOLID)) {
+        abar[nb.idx] = a1;
+        abar[n + nb.idx] = 0.f;
+        abar[2 * n + nb.idx] = 0.f;
+        abar[3 * n + nb.idx] = a2;
+        abar[4 * n + nb.idx] = 0.f;
+        abar[5 * n + nb.idx] = 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Seed at the final time: dL/df_i = dL/drho, identical over i; it is stored
 // as lambda_loc = 0 plus rhobar = (rho2, -rho1) / (rho1+rho2)^2 / |R|.
 // ---------------------------------------------------------------------------
@@ -389,6 +510,27 @@ void launch_adj_seed(const Pops<CF>& P, const int* fid, const uint32_t* nbm, con
         hipLaunchKernelGGL(k_adj_seed<true>, rows(g), kBlock, 0, s, P, fid, nbm, region, g, loss, lam, rbar);
     else
         hipLaunchKernelGGL(k_adj_seed<false>, rows(g), kBlock, 0, s, P, fid, nbm, region, g, loss, lam, rbar);
+}
+
+void launch_loss_flux(const Pops<CF>& P, const int* fid, const uint32_t* nbm, const uint8_t* region,
+                      const float2* psi, const Geo& g, const Phys& ph, int odd, double* partial, double* out,
+                      hipStream_t s) {
+    if (odd)
+        hipLaunchKernelGGL(k_loss_flux_partial<true>, rows(g), kBlock, 0, s, P, fid, nbm, region, psi, g, ph, partial);
+    else
+        hipLaunchKernelGGL(k_loss_flux_partial<false>, rows(g), kBlock, 0, s, P, fid, nbm, region, psi, g, ph,
+                           partial);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, s, (const double*)partial, loss_blocks(g), out);
+}
+
+void launch_adj_seed_flux(const Pops<CF>& P, const int* fid, const uint32_t* nbm, const uint8_t* region,
+                          const float2* psi, const Geo& g, const Phys& ph, int odd, float* lam, float* abar,
+                          hipStream_t s) {
+    if (odd)
+        hipLaunchKernelGGL(k_adj_seed_flux<true>, rows(g), kBlock, 0, s, P, fid, nbm, region, psi, g, ph, lam, abar);
+    else
+        hipLaunchKernelGGL(k_adj_seed_flux<false>, rows(g), kBlock, 0, s, P, fid, nbm, region, psi, g, ph, lam,
+                           abar);
 }
 
 void launch_node_of(const int* fid, const Geo& g, int* node_of, hipStream_t s) {

@@ -10,6 +10,13 @@ void launch_loss(const Pops<CodecF32>& P, const int* fid, const uint32_t* nbm, c
                  const Geo& g, int odd, double* partial, double* out, hipStream_t s);
 void launch_adj_seed(const Pops<CodecF32>& P, const int* fid, const uint32_t* nbm, const uint8_t* region,
                      const Geo& g, int odd, const double* loss, float* lam, float2* rbar, hipStream_t s);
+// outlet flux: out[0] = mean of rho1 u_x over the region's fluid nodes, out[1] = their count
+void launch_loss_flux(const Pops<CodecF32>& P, const int* fid, const uint32_t* nbm, const uint8_t* region,
+                      const float2* psi, const Geo& g, const Phys& ph, int odd, double* partial, double* out,
+                      hipStream_t s);
+void launch_adj_seed_flux(const Pops<CodecF32>& P, const int* fid, const uint32_t* nbm, const uint8_t* region,
+                          const float2* psi, const Geo& g, const Phys& ph, int odd, float* lam, float* abar,
+                          hipStream_t s);
 // node_of[k] = lattice index of fluid id k
 void launch_node_of(const int* fid, const Geo& g, int* node_of, hipStream_t s);
 void launch_adj_collide(const Pops<CodecF32>& P, const int* fid, const int* node_of, int nfluid, const uint32_t* nbm,

@@ -511,6 +511,21 @@ mclbm_status mclbm_loss_snw(mclbm_lattice* lat, const uint8_t* d_region, double*
     return MCLBM_OK;
 }
 
+mclbm_status mclbm_loss_flux(mclbm_lattice* lat, const uint8_t* d_region, double* h_L) {
+    if (!lat || !d_region || !h_L) return fail(MCLBM_EINVAL, "NULL argument");
+    if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    lat->fill_psi();
+    launch_loss_flux(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, lat->R((int)(lat->t & 1)), lat->g,
+                     lat->ph, (int)(lat->t & 1), lat->partial(), lat->diag_out(), lat->stream);
+    HIP_TRY(hipGetLastError());
+    double out[2];
+    HIP_TRY(hipMemcpyAsync(out, lat->diag_out(), sizeof(out), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    *h_L = out[0] * out[1];  // mean times count: the sum over the region
+    return MCLBM_OK;
+}
+
 mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes) {
     if (!lat || !bytes || nsteps < 1 || every < 1) return fail(MCLBM_EINVAL, "bad argument");
     *bytes = (size_t)((nsteps + every - 1) / every) * state_slot_bytes(lat->L);
@@ -608,8 +623,10 @@ static hipError_t ensure_aux(mclbm_lattice* lat) {
     return hipSuccess;
 }
 
-mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
-                                const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
+enum class LossKind { Snw, Flux };
+
+static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, int32_t every, const void* d_ckpt,
+                             const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
     if (!lat || !d_ckpt || !d_region || !d_work || !d_grad_xi || nsteps < 1 || every < 1)
         return fail(MCLBM_EINVAL, "bad argument");
     if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
@@ -633,11 +650,24 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
     launch_node_of(lat->fid(), g, W.node_of, s);
     launch_zero(d_grad_xi, n * sizeof(double), s);
     // seed from the final state (the lattice's current populations)
-    launch_loss(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->partial(),
-                lat->diag_out(), s);
     int cur = 0;  // lam[cur], rbar[cur] hold dL/df at the time level being processed
-    launch_adj_seed(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->diag_out(),
-                    W.lam[cur], W.rbar[cur], s);
+    if (kind == LossKind::Snw) {
+        launch_loss(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1), lat->partial(),
+                    lat->diag_out(), s);
+        launch_adj_seed(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, g, (int)(t_end & 1),
+                        lat->diag_out(), W.lam[cur], W.rbar[cur], s);
+    } else {
+        // the flux depends on the forces at the final time: its seed holds a
+        // local part and the adjoint of the pseudopotential sums, which the
+        // IVSD and density adjoints turn into the direct xi term and the
+        // neighbours' density adjoint
+        lat->fill_psi();
+        const float2* psi_end = lat->R((int)(t_end & 1));
+        launch_adj_seed_flux(lat->pops<CodecF32>(), lat->fid(), lat->nbm(), d_region, psi_end, g, lat->ph,
+                             (int)(t_end & 1), W.lam[cur], W.abar, s);
+        launch_adj_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi_end, W.abar, g, W.gacc, W.nbar, s);
+        launch_adj_rho(W.node_of, lat->nfluid, lat->nbm(), W.abar, W.nbar, g, W.rbar[cur], s);
+    }
     // Segment seg is recomputed into buffer seg & 1 on the auxiliary stream
     // and reversed from it on the lattice's stream; the recompute of segment
     // seg - 1 runs while segment seg is reversed (the two touch disjoint
@@ -711,6 +741,16 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
     launch_grad_scatter(lat->list(), lat->nbound, W.gacc, d_grad_xi, s);
     HIP_TRY(hipGetLastError());
     return MCLBM_OK;
+}
+
+mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
+                                const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
+    return gradient(lat, LossKind::Snw, nsteps, every, d_ckpt, d_region, d_work, work_bytes, d_grad_xi);
+}
+
+mclbm_status mclbm_gradient_flux(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
+                                 const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
+    return gradient(lat, LossKind::Flux, nsteps, every, d_ckpt, d_region, d_work, work_bytes, d_grad_xi);
 }
 
 static void drop_events(mclbm_lattice* lat) {

@@ -66,10 +66,12 @@ SIGNATURES = [
     ("mclbm_save_state", _I32, [_VP, _VP]),
     ("mclbm_load_state", _I32, [_VP, _VP]),
     ("mclbm_loss_snw", _I32, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
+    ("mclbm_loss_flux", _I32, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("mclbm_checkpoint_bytes", _I32, [_VP, _I32, _I32, _SZP]),
     ("mclbm_adjoint_work_bytes", _I32, [_VP, _I32, _SZP]),
     ("mclbm_step_checkpointed", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t]),
     ("mclbm_gradient_snw", _I32, [_VP, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    ("mclbm_gradient_flux", _I32, [_VP, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     ("mclbm_set_open_x", _I32, [_VP, _I32, ctypes.c_double, ctypes.c_double]),
     ("mclbm_open_x_pressure", _I32, [_VP, ctypes.POINTER(ctypes.c_double)]),
     ("mclbm_profile", _I32, [_VP, _I32]),
@@ -245,6 +247,13 @@ class Lattice:
         _check(_lib.mclbm_loss_snw(self._h, _ptr(reg), ctypes.byref(L)), "loss_snw")
         return L.value
 
+    def loss_flux(self, region) -> float:
+        """Outlet flux sum_{fluid x in region} rho1 u_x at the current time level."""
+        reg = self._region(region)
+        L = ctypes.c_double()
+        _check(_lib.mclbm_loss_flux(self._h, _ptr(reg), ctypes.byref(L)), "loss_flux")
+        return L.value
+
     def step_checkpointed(self, nsteps: int, every: int) -> torch.Tensor:
         """Advance nsteps, keeping a checkpoint every `every` steps; returns the buffer."""
         b = ctypes.c_size_t()
@@ -255,15 +264,23 @@ class Lattice:
         return ck
 
     def gradient_snw(self, nsteps: int, every: int, checkpoints: torch.Tensor, region) -> torch.Tensor:
-        """dL/dxi (float64, shape (nz, ny, nx)) of the loss at the current time level
-        through the nsteps recorded by step_checkpointed."""
+        """dL/dxi (float64, shape (nz, ny, nx)) of the smooth non-wetting saturation
+        at the current time level through the nsteps recorded by step_checkpointed."""
+        return self._gradient(_lib.mclbm_gradient_snw, "gradient_snw", nsteps, every, checkpoints, region)
+
+    def gradient_flux(self, nsteps: int, every: int, checkpoints: torch.Tensor, region) -> torch.Tensor:
+        """dL/dxi of the outlet flux (loss_flux) at the current time level through
+        the nsteps recorded by step_checkpointed."""
+        return self._gradient(_lib.mclbm_gradient_flux, "gradient_flux", nsteps, every, checkpoints, region)
+
+    def _gradient(self, fn, what, nsteps, every, checkpoints, region):
         reg = self._region(region)
         b = ctypes.c_size_t()
         _check(_lib.mclbm_adjoint_work_bytes(self._h, int(every), ctypes.byref(b)), "adjoint_work_bytes")
         work = torch.empty(b.value, dtype=torch.uint8, device=self.device)
         grad = torch.empty(self.dims, dtype=torch.float64, device=self.device)
-        _check(_lib.mclbm_gradient_snw(self._h, int(nsteps), int(every), _ptr(checkpoints), _ptr(reg),
-                                       _ptr(work), b.value, _ptr(grad)), "gradient_snw")
+        _check(fn(self._h, int(nsteps), int(every), _ptr(checkpoints), _ptr(reg), _ptr(work), b.value, _ptr(grad)),
+               what)
         self._keep = (reg, work)
         return grad
 

@@ -142,3 +142,73 @@ def test_adjoint_entry_points_refuse_unsupported_lattices():
         opened.step_checkpointed(4, 2)
     opened.step(2)
     assert opened.time == 2
+
+
+def _oracle_flux(shape, solid, xi64, rho, tau, G, g, steps, region):
+    o = Oracle(OracleParams(shape, tau=tau, G=G, g=g), solid, xi64)
+    o.init_equilibrium(rho.astype(np.float32).astype(np.float64))
+    o.run(steps)
+    r, _, _, u = o.fields()
+    sel = (solid == 0) & (region != 0)
+    return float((r[0] * u[0])[sel].sum())
+
+
+@pytest.mark.parametrize("steps,every", [(1, 1), (2, 1), (9, 4)])
+def test_flux_gradient_against_oracle_fd(steps, every):
+    """Outlet flux sum rho1 u_x over the plane x = nx - 3: loss against the
+    oracle's fields, gradient against its central differences at sampled
+    boundary voxels and along a random direction over all of them."""
+    import torch
+    from paper_2207_01534_amd.autograd import OutletFluxLoss
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams
+    shape = (12, 10, 8)
+    nx, ny, nz = shape
+    print(f"[case] flux adjoint {shape} steps={steps} every={every}", flush=True)
+    solid = wl.random_mask(shape, 0.25, seed=91)
+    xi = wl.uniform_xi(solid, -0.4, 0.4, seed=92)
+    rho = wl.tanh_droplet(shape, 3.0)
+    rho[:, solid != 0] = 0
+    tau, G, g = (1.5, 0.6), 3.5, ((3e-4, 0.0, 0.0), (1e-4, 0.0, 0.0))
+    region = np.zeros((nz, ny, nx), np.uint8)
+    region[:, :, nx - 3] = 1
+    lat = Lattice(LatticeParams(shape=shape, tau=tau, G=G, g=g), torch.as_tensor(solid), torch.as_tensor(xi), None)
+    xi_t = torch.tensor(xi, device="cuda", requires_grad=True)
+    L = OutletFluxLoss.apply(xi_t, lat, torch.as_tensor(rho.astype(np.float32), device="cuda"),
+                             torch.as_tensor(region, device="cuda"), steps, every)
+    L.backward()
+    torch.cuda.synchronize()
+    grad = xi_t.grad.double().cpu().numpy()
+    xi64 = xi.astype(np.float64)
+    L_orc = _oracle_flux(shape, solid, xi64, rho, tau, G, g, steps, region)
+    L_gpu = float(L.detach())
+    print(f"[flux] L_gpu={L_gpu:.6e} L_orc={L_orc:.6e}", flush=True)
+    assert L_gpu == pytest.approx(L_orc, rel=1e-4, abs=1e-7 * max(abs(L_orc), 1e-3))
+    bs = _boundary_solid(solid)
+    assert np.all(grad[~bs] == 0.0)
+    rng = np.random.default_rng(100 + steps)
+    cand = np.argwhere(bs)
+    pick = cand[rng.choice(len(cand), size=10, replace=False)]
+    eps = 1e-3
+    fd = []
+    for z, y, x in pick:
+        xp, xm = xi64.copy(), xi64.copy()
+        xp[z, y, x] += eps
+        xm[z, y, x] -= eps
+        fd.append((_oracle_flux(shape, solid, xp, rho, tau, G, g, steps, region)
+                   - _oracle_flux(shape, solid, xm, rho, tau, G, g, steps, region)) / (2 * eps))
+    fd = np.array(fd)
+    adj = np.array([grad[z, y, x] for z, y, x in pick])
+    scale = np.abs(fd).max()
+    err = np.abs(adj - fd).max() / scale
+    print(f"[flux-adjoint] steps={steps} max|fd|={scale:.3e} rel err={err:.3e}", flush=True)
+    assert scale > 0
+    assert err <= 1e-3
+    v = np.where(bs, rng.standard_normal(bs.shape), 0.0)
+    v /= np.abs(v).max()
+
+    def directional(e):
+        return (_oracle_flux(shape, solid, xi64 + e * v, rho, tau, G, g, steps, region)
+                - _oracle_flux(shape, solid, xi64 - e * v, rho, tau, G, g, steps, region)) / (2 * e)
+    dd, dd_half = directional(eps), directional(eps / 2)
+    assert dd_half == pytest.approx(dd, rel=1e-5, abs=1e-6 * scale)
+    assert float((grad * v).sum()) == pytest.approx(dd_half, rel=1e-3, abs=1e-3 * scale)
