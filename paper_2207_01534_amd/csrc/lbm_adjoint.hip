@@ -17,7 +17,10 @@
 //                  rhobar(z) = -sum_k w_k e_k . Abar(z+e_k)
 //                              + sum_{solid z+e_m} w_m Nbar(z+e_m).
 // dL/df_i(t) at a fluid node is lambda_loc_i + rhobar, kept as the two parts
-// and added where the next reverse step gathers them.
+// and added where the next reverse step gathers them.  Both are indexed by
+// fluid id (plane stride np, like the populations), so their gathers touch
+// no solid slots; Abar and Nbar stay indexed by lattice node, since solid
+// neighbours read them.
 #include "lbm_adjoint.hpp"
 
 namespace mclbm {
@@ -197,12 +200,15 @@ __global__ __launch_bounds__(256) void k_adj_seed_flux(Pops<CF> P, const int* __
         a1 = -0.5f * ph.G * q.rho[0] * q.rho[1] * inv;
         a2 = -0.5f * ph.G * q.rho[0] * q.rho[0] * inv;
     }
+    if (m & SELF_SOLID) return;
+    const uint32_t kf = (uint32_t)fid[nb.idx];
+    const size_t np = (size_t)g.np;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        lam[(size_t)i * n + nb.idx] = l0 + DX[i] * lj;
-        lam[(size_t)(Q + i) * n + nb.idx] = l1 + DX[i] * lj;
+        lam[(size_t)i * np + kf] = l0 + DX[i] * lj;
+        lam[(size_t)(Q + i) * np + kf] = l1 + DX[i] * lj;
     }
-    if (!(m & SELF_SOLID)) {
+    {
         abar[nb.idx] = a1;
         abar[n + nb.idx] = 0.f;
         abar[2 * n + nb.idx] = 0.f;
@@ -228,19 +234,22 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const int* __restr
     if (x >= g.nx || y >= g.ny) return;
     const Nb nb(x, y, z, g);
     const size_t n = (size_t)g.n;
-    for (int k = 0; k < 2 * Q; ++k) lam[k * n + nb.idx] = 0.0f;
     const uint32_t m = nbm[nb.idx];
+    if (m & SELF_SOLID) return;
+    const uint32_t kf = (uint32_t)fid[nb.idx];
+    const size_t np = (size_t)g.np;
+    for (int k = 0; k < 2 * Q; ++k) lam[(size_t)k * np + kf] = 0.0f;
     float2 r = make_float2(0.f, 0.f);
-    if (!(m & SELF_SOLID) && region[nb.idx] && loss[1] > 0) {
+    if (region[nb.idx] && loss[1] > 0) {
         float f[2][Q];
-        load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx],
+        load_node<CF, ODD>(f, P, nullptr, m, nb, kf,
                            [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
         const double r0 = sum19(f[0]), r1 = sum19(f[1]);
         const double rt = r0 + r1;
         const double s = 1.0 / (rt * rt * loss[1]);
         r = make_float2((float)(r1 * s), (float)(-r0 * s));
     }
-    rbar[nb.idx] = r;
+    rbar[kf] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +271,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
     const int idx = node_of[kf];
     const int x = idx % g.nx, y = (idx / g.nx) % g.ny, z = idx / (g.nx * g.ny);
     const Nb nb(x, y, z, g);
-    const size_t n = (size_t)g.n;
+    const size_t n = (size_t)g.n, np = (size_t)g.np;
     const uint32_t m = nbm[nb.idx];
     // forward quantities of this node at time t
     float f[2][Q];
@@ -293,17 +302,17 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
     // lambda* = dL/df*: the adjoint of streaming gathers from downstream
     float ls[2][Q];
     {
-        const float2 rb0 = rbar_next[nb.idx];
-        ls[0][0] = lam_next[nb.idx] + rb0.x;
-        ls[1][0] = lam_next[(size_t)Q * n + nb.idx] + rb0.y;
+        const float2 rb0 = rbar_next[kf];
+        ls[0][0] = lam_next[kf] + rb0.x;
+        ls[1][0] = lam_next[(size_t)Q * np + kf] + rb0.y;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const bool wall = (m >> i) & 1u;
-            const uint32_t at = wall ? nb.idx : nb.at(i, +1);
+            const uint32_t at = wall ? (uint32_t)kf : (uint32_t)fid[nb.at(i, +1)];
             const int dir = wall ? opp(i) : i;
             const float2 rb = rbar_next[at];
-            ls[0][i] = lam_next[(size_t)dir * n + at] + rb.x;
-            ls[1][i] = lam_next[(size_t)(Q + dir) * n + at] + rb.y;
+            ls[0][i] = lam_next[(size_t)dir * np + at] + rb.x;
+            ls[1][i] = lam_next[(size_t)(Q + dir) * np + at] + rb.y;
         }
     }
 
@@ -379,7 +388,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const float ej = DX[i] * Pbar[0] + DY[i] * Pbar[1] + DZ[i] * Pbar[2];
-            lam_cur[(size_t)(s * Q + i) * n + nb.idx] = keep * ls[s][i] + ej + rb[s];
+            lam_cur[(size_t)(s * Q + i) * np + kf] = keep * ls[s][i] + ej + rb[s];
         }
 }
 
@@ -461,7 +470,7 @@ __global__ __launch_bounds__(256) void k_adj_rho(const int* __restrict__ node_of
         r.x += solid ? weight(i) * nv[i].x : 0.0f;
         r.y += solid ? weight(i) * nv[i].y : 0.0f;
     }
-    rbar[nb.idx] = r;
+    rbar[kf] = r;
 }
 
 // node_of[fid[idx]] = idx for every fluid node.

@@ -535,9 +535,9 @@ mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, in
 struct AdjointWork {
     char* seg[2];   // two segment buffers of `every` state slots
     char* psi[2];   // and of `every` psi-hat fields (n float2 each)
-    float* lam[2];  // [2][19][n]
-    float* abar;    // [6][n]
-    float2* rbar[2];
+    float* lam[2];   // [2][19][np], by fluid id
+    float* abar;     // [6][n], by lattice node (read at solid neighbours)
+    float2* rbar[2]; // [np], by fluid id
     float2* nbar;
     double* gacc;   // per boundary-list entry
     int* node_of;   // lattice index of each fluid id
@@ -557,11 +557,12 @@ static AdjointWork adjoint_layout(const mclbm_lattice* lat, int32_t every, char*
         w.seg[b] = take((size_t)every * state_slot_bytes(lat->L));
         w.psi[b] = take((size_t)every * align_up(n * sizeof(float2), kAlign));
     }
-    w.lam[0] = (float*)take(2 * Q * n * sizeof(float));
-    w.lam[1] = (float*)take(2 * Q * n * sizeof(float));
+    const size_t np = (size_t)lat->L.np;  // the adjoint of the populations is indexed by fluid id
+    w.lam[0] = (float*)take(2 * Q * np * sizeof(float));
+    w.lam[1] = (float*)take(2 * Q * np * sizeof(float));
     w.abar = (float*)take(6 * n * sizeof(float));
-    w.rbar[0] = (float2*)take(n * sizeof(float2));
-    w.rbar[1] = (float2*)take(n * sizeof(float2));
+    w.rbar[0] = (float2*)take(np * sizeof(float2));
+    w.rbar[1] = (float2*)take(np * sizeof(float2));
     w.nbar = (float2*)take(n * sizeof(float2));
     w.gacc = (double*)take(n * sizeof(double));
     w.node_of = (int*)take((size_t)lat->L.cap * sizeof(int));
