@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_loss_flux_partial(Pops<CF> P, const int
 //   dL/drho2 = rho1 ((g2_x - G A1_x)/2 - u_x) / rho,   dL/dj_x = rho1 / rho,
 //   dL/dA1_x = -G rho1 rho2 / (2 rho),               dL/dA2_x = -G rho1^2 / (2 rho);
 // so lambda_loc_i^s = dL/drho^s + e_ix rho1/rho, and Abar carries the A terms
-// (planes 0..2: A of component 1, 3..5: A of component 2) to the IVSD and
+// (per axis a pair: A of component 1, A of component 2) to the IVSD and
 // density adjoints, which return the neighbours' share and the direct xi term.
 template <bool ODD>
 __global__ __launch_bounds__(256) void k_adj_seed_flux(Pops<CF> P, const int* __restrict__ fid,
@@ -209,12 +209,10 @@ __global__ __launch_bounds__(256) void k_adj_seed_flux(Pops<CF> P, const int* __
         lam[(size_t)(Q + i) * np + kf] = l1 + DX[i] * lj;
     }
     {
-        abar[nb.idx] = a1;
-        abar[n + nb.idx] = 0.f;
-        abar[2 * n + nb.idx] = 0.f;
-        abar[3 * n + nb.idx] = a2;
-        abar[4 * n + nb.idx] = 0.f;
-        abar[5 * n + nb.idx] = 0.f;
+        float2* ab = reinterpret_cast<float2*>(abar);
+        ab[nb.idx] = make_float2(a1, a2);
+        ab[n + nb.idx] = make_float2(0.f, 0.f);
+        ab[2 * n + nb.idx] = make_float2(0.f, 0.f);
     }
 }
 
@@ -378,8 +376,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        abar[(size_t)a * n + nb.idx] = -ph.G * rho[1] * Fbar[1][a];        // adjoint of A^(1)
-        abar[(size_t)(3 + a) * n + nb.idx] = -ph.G * rho[0] * Fbar[0][a];  // adjoint of A^(2)
+        reinterpret_cast<float2*>(abar)[(size_t)a * n + nb.idx] =
+            make_float2(-ph.G * rho[1] * Fbar[1][a], -ph.G * rho[0] * Fbar[0][a]);  // adjoints of A^(1), A^(2)
     }
     // local part of dL/df_i(t): direct term, momentum term, density term
     const float keep = 1.0f - om;
@@ -400,9 +398,10 @@ __device__ __forceinline__ float2 psi_adjoint(const float* __restrict__ abar, co
         const uint32_t at = nb.at(k, +1);
         const float w = weight(k);
         float d0 = 0.f, d1 = 0.f;
-        if (DX[k]) { d0 += DX[k] * abar[at]; d1 += DX[k] * abar[3 * n + at]; }
-        if (DY[k]) { d0 += DY[k] * abar[n + at]; d1 += DY[k] * abar[4 * n + at]; }
-        if (DZ[k]) { d0 += DZ[k] * abar[2 * n + at]; d1 += DZ[k] * abar[5 * n + at]; }
+        const float2* ab = reinterpret_cast<const float2*>(abar);
+        if (DX[k]) { const float2 v = ab[at]; d0 += DX[k] * v.x; d1 += DX[k] * v.y; }
+        if (DY[k]) { const float2 v = ab[n + at]; d0 += DY[k] * v.x; d1 += DY[k] * v.y; }
+        if (DZ[k]) { const float2 v = ab[2 * n + at]; d0 += DZ[k] * v.x; d1 += DZ[k] * v.y; }
         p0 -= w * d0;
         p1 -= w * d1;
     }

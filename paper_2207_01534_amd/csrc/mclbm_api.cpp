@@ -536,7 +536,7 @@ struct AdjointWork {
     char* seg[2];   // two segment buffers of `every` state slots
     char* psi[2];   // and of `every` psi-hat fields (n float2 each)
     float* lam[2];   // [2][19][np], by fluid id
-    float* abar;     // [6][n], by lattice node (read at solid neighbours)
+    float* abar;     // [3][n] pairs (component 1, component 2), by lattice node (read at solid neighbours)
     float2* rbar[2]; // [np], by fluid id
     float2* nbar;
     double* gacc;   // per boundary-list entry
