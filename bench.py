@@ -5,8 +5,10 @@ A step is one pass of the whole hot path over the lattice: densities,
 virtual solid densities (IVSD), forces, forced SRT collision and streaming
 with bounce-back, all in the HIP kernels of libmclbm.so.  The default
 workload is the 512^3 sphere pack (radius 12, porosity ~0.38), single-buffer
-streaming, FP32 storage; the FP16 and BF16 offset-storage forms are timed in
-the same run and reported under "variants".
+streaming, FP32 storage; the FP16 and BF16 offset-storage forms, and the FP32
+step with open inlet/outlet planes along x (the drainage drive of Sec. 4.1, on
+the same pack with 10-plane fluid reservoirs at both x ends, timed open and
+periodic), are timed in the same run and reported under "variants".
 
 Prints one JSON line.  ``value`` is MLUPS over all lattice nodes (solid
 included) with the state resident in HBM; the roofline object prices the
@@ -44,13 +46,27 @@ def describe(w):
             + f", tau=({w.tau[0]}, {w.tau[1]}), G={w.G}, porosity {w.n_fluid / w.n_nodes:.4f}")
 
 
-def run_gpu(w, storage, steps, warmup):
+# Open-plane variant: component 1 imposed at the inlet slightly above the bulk
+# density it takes at G = 3.5 (about 1.05), component 2 at the outlet at it.
+OPEN_RHO = (1.07, 1.05)
+OPEN_RESERVOIR = 10
+
+
+def _open_applies(w):
+    """The open-plane variant runs on porous samples long enough in x for two
+    reservoirs and the sample between them."""
+    return bool((w.solid != 0).any()) and w.shape[0] >= 4 * OPEN_RESERVOIR
+
+
+def run_gpu(w, storage, steps, warmup, open_x=None):
     import torch
     from paper_2207_01534_amd.lattice import Lattice, LatticeParams, Storage
     st = {"f32": Storage.F32, "f16": Storage.F16, "bf16": Storage.BF16}[storage]
     p = LatticeParams(shape=w.shape, tau=w.tau, G=w.G, g=w.g, storage=st, fluid_capacity=w.n_fluid)
     lat = Lattice(p, torch.as_tensor(w.solid), torch.as_tensor(w.xi),
                   torch.as_tensor(w.rho.astype(np.float32)))
+    if open_x is not None:
+        lat.set_open_x(*open_x)
     lat.step(warmup)
     torch.cuda.synchronize()
     lat.profile(True)
@@ -232,8 +248,9 @@ def main():
     ap.add_argument("--workload", default="spheres512")
     ap.add_argument("--shape", default=None, help="override the workload's shape, e.g. 512,512,512")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--variants", default="f16,bf16",
-                    help="extra storage forms timed in the same run (comma list, '' for none)")
+    ap.add_argument("--variants", default="f16,bf16,open",
+                    help="extra forms timed in the same run: storage forms and 'open' (FP32 with "
+                         "open x planes); comma list, '' for none")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
@@ -263,8 +280,23 @@ def main():
     _log(f"{args.storage}: {main_res['mlups']:.0f} MLUPS")
     variants = {}
     for v in [s for s in args.variants.split(",") if s and s != args.storage]:
+        if v not in POP_BYTES and v != "open":
+            ap.error(f"unknown variant {v!r}")
         _log(f"timing variant {v}")
-        variants[v] = run_gpu(w, v, args.steps, args.warmup)
+        if v == "open":
+            if not _open_applies(w):
+                _log("open: skipped (not a porous sample with room for the reservoirs)")
+                continue
+            wo = wl.open_drainage(w, OPEN_RESERVOIR)
+            variants[v] = run_gpu(wo, "f32", args.steps, args.warmup, open_x=OPEN_RHO)
+            periodic = run_gpu(wo, "f32", args.steps, args.warmup)
+            variants[v]["open_x"] = {
+                "rho1_in": OPEN_RHO[0], "rho2_out": OPEN_RHO[1], "reservoir_planes": OPEN_RESERVOIR,
+                "fluid_nodes": wo.n_fluid, "body_force": 0.0,
+                "periodic_ms_per_step": round(periodic["ms_per_step"], 4),
+                "extra_ms_per_step": round(variants[v]["ms_per_step"] - periodic["ms_per_step"], 4)}
+        else:
+            variants[v] = run_gpu(w, v, args.steps, args.warmup)
         _log(f"{v}: {variants[v]['mlups']:.0f} MLUPS")
 
     adjoint = None
@@ -285,6 +317,8 @@ def main():
     _log(f"plain copy: {copy_gbs:.0f} GB/s")
 
     def traffic_of(res, storage):
+        if storage not in POP_BYTES:
+            return None, None
         t = measured_traffic(name, storage)
         ms = res["kernels_ms_avg"]["collide_stream"]
         return t, (round(t / (ms * 1e-3) / 1e9, 1) if t else None)
@@ -326,7 +360,9 @@ def main():
                          "gbs_alg_step": round(v["gbs_alg_step"], 1),
                          "collide_stream_gbs": round(v["collide_stream_gbs"], 1),
                          "collide_stream_traffic_gbs": traffic_of(v, k)[1],
-                         "kernels_ms_avg": {kk: round(vv, 4) for kk, vv in v["kernels_ms_avg"].items()}}
+                         "nonfinite": v["nonfinite"],
+                         "kernels_ms_avg": {kk: round(vv, 4) for kk, vv in v["kernels_ms_avg"].items()},
+                         **({"open_x": v["open_x"]} if "open_x" in v else {})}
                      for k, v in variants.items()},
     }
     print(json.dumps(out), flush=True)

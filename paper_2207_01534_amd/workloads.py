@@ -153,6 +153,40 @@ def inlet_drainage_rho(solid, buffer=3, width=5.0):
     return rho
 
 
+def open_drainage_rho(solid, front=6.0, width=5.0):
+    """Initial densities for a drainage driven through open x planes: component 1
+    fills the inlet side up to a front at x = front (inside the fluid buffer
+    layers and the first pore layer), component 2 the rest, outlet buffer
+    included, with the diffuse tanh interface of the paper's initialisation
+    (Sec. 3.1, Eq. 16) in one dimension, width W = 5.  Unlike
+    inlet_drainage_rho the outlet holds the displaced component, as the
+    outlet condition (component 2 imposed) requires."""
+    nz, ny, nx = solid.shape
+    x = np.arange(nx, dtype=np.float64)
+    t = np.tanh(2.0 * (x - front) / width)
+    r1 = 0.5 * (RHO_MAJOR + RHO_MINOR) - 0.5 * (RHO_MAJOR - RHO_MINOR) * t
+    r2 = (RHO_MAJOR + RHO_MINOR) - r1
+    rho = np.stack([np.broadcast_to(r1, (nz, ny, nx)), np.broadcast_to(r2, (nz, ny, nx))]).copy()
+    rho[:, solid != 0] = 0.0
+    return rho
+
+
+def open_drainage(w: "Workload", reservoir: int = 10) -> "Workload":
+    """The workload's sample set up for a drainage driven through open x planes:
+    the first and last `reservoir` x planes are cleared of solid (pure-fluid
+    inlet and outlet reservoirs, as the paper adds in front of and behind its
+    samples, Sec. 4.1), component 1 fills the inlet reservoir up to two planes
+    short of the sample (open_drainage_rho), and the body force is zero (the
+    imposed inlet/outlet densities drive the flow)."""
+    solid = w.solid.copy()
+    solid[:, :, :reservoir] = 0
+    solid[:, :, solid.shape[2] - reservoir:] = 0
+    xi = np.where(solid != 0, w.xi, 0).astype(np.float32)
+    rho = open_drainage_rho(solid, front=reservoir - 2.0)
+    info = dict(w.info, reservoir=reservoir)
+    return Workload(w.name + "+open", w.shape, solid, xi, rho, w.tau, w.G, ((0, 0, 0), (0, 0, 0)), w.steps, info)
+
+
 def contact_angle_cubic(xi):
     """The paper's fitted contact angle (degrees) versus xi (Sec. 3.2)."""
     return 47.4136 * xi ** 3 - 23.4513 * xi ** 2 + 89.7938 * xi + 91.2324

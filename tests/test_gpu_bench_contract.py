@@ -1,6 +1,7 @@
 """The benchmark's output contract on the GPU: one JSON line with the
 throughput, the roofline of the dominant kernel and the oracle's host
-baseline, on the small droplet workload (a few seconds)."""
+baseline, on the small droplet workload (a few seconds); and the open-plane
+variant on a small sphere pack."""
 import json
 import os
 import sys
@@ -39,3 +40,22 @@ def test_bench_prints_one_complete_json_line(monkeypatch, capsys):
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
     assert set(d["variants"]) == {"f16", "bf16"}
+
+
+def test_bench_open_plane_variant(monkeypatch, capsys):
+    sys.path.insert(0, ROOT)
+    import bench
+    argv = ["bench.py", "--workload", "spheres128", "--shape", "64,64,64", "--steps", "20", "--warmup", "4",
+            "--no-cpu-baseline", "--no-adjoint", "--variants", "open"]
+    print("[case] " + " ".join(argv), flush=True)
+    capsys.readouterr()
+    monkeypatch.setattr(sys, "argv", argv)
+    bench.main()
+    out = capsys.readouterr().out
+    d = json.loads([l for l in out.splitlines() if l.strip()][-1])
+    v = d["variants"]["open"]
+    assert v["mlups"] > 0 and v["nonfinite"] == 0
+    o = v["open_x"]
+    assert o["rho1_in"] == bench.OPEN_RHO[0] and o["rho2_out"] == bench.OPEN_RHO[1]
+    assert o["periodic_ms_per_step"] > 0 and o["fluid_nodes"] > d["config"]["fluid_nodes"]
+    assert v["collide_stream_traffic_gbs"] is None
