@@ -23,6 +23,7 @@
 //                   equilibrium at their mirrored densities so they stay finite.
 // Planes 0, 1, 2, nx-3, nx-2 and nx-1 must be fluid (checked on the host).
 #include "lbm_open.hpp"
+#include "lbm_tiles.hpp"
 
 namespace mclbm {
 
@@ -62,22 +63,6 @@ __device__ __forceinline__ float read_pop(const Pops<C>& P, int s, const OpenSlo
     }
 }
 
-// Store f_i of component s; returns the value a decoder will read back.
-template <class C>
-__device__ __forceinline__ float write_pop(const Pops<C>& P, int s, const OpenSlot& q, int i, float v,
-                                           const float2* psi, int np) {
-    float rw = 0.0f, rt = 0.0f, inv = 0.0f;
-    if constexpr (C::kRef) {
-        const float2 r = ld(psi, q.writer);
-        rw = s ? r.y : r.x;
-        rt = r.x + r.y;
-        inv = inv_total(r);
-    }
-    const typename C::T h = C::enc(v, weight(i), rw, inv);
-    *P.at(s, q.dir, q.id, np) = h;
-    return C::dec(h, weight(i), rw, rt);
-}
-
 // Eq. (2) at one direction.
 __device__ __forceinline__ float feq(int i, float rho, const float (&u)[3], float usq) {
     const float eu = DX[i] * u[0] + DY[i] * u[1] + DZ[i] * u[2];
@@ -92,34 +77,110 @@ __global__ void k_open_mirror(float2* __restrict__ psi, Geo g) {
     psi[row + g.nx - 1] = psi[row + g.nx - 3];
 }
 
-// One thread per (y, z) row and side.  odd: parity of the time level the
-// populations are at (the one just reached); psi: densities of the level
-// before, the codec reference of every value written in the last step.
+// Rebuild launch shape: one thread per (y, z) row and side, a block of
+// 256 threads per 16 x 16 patch of rows of one side, patches dealt to the
+// XCDs in contiguous runs (active_of_block).  A row's three nodes (ghost,
+// boundary, next inwards) sit in consecutive slots of every direction plane,
+// and at odd levels their slots are addressed through the fluid ids of the
+// rows next to it; the block stages those ids once in LDS (five x positions
+// over the patch and a one-row halo in y and z), and every slot moves both
+// components in one access where both are read or written.
+constexpr int OPEN_PATCH = 16;
+constexpr int OPEN_XS = 5, OPEN_H = OPEN_PATCH + 2;
+
+__host__ __device__ inline int open_patches(const Geo& g) {
+    return ((g.ny + OPEN_PATCH - 1) / OPEN_PATCH) * ((g.nz + OPEN_PATCH - 1) / OPEN_PATCH);
+}
+
+// Slot of f_i at staged x position k of the thread's row (AA pattern): the
+// direction plane, the fluid id, and whether x - e_i is solid (fluid id -1).
+struct StagedSlot {
+    int dir;
+    uint32_t id;
+    bool up_solid;
+};
+
+__device__ __forceinline__ StagedSlot staged_slot(int i, bool odd, int k, int ly, int lz,
+                                                  const int (&sf)[OPEN_XS][OPEN_H][OPEN_H]) {
+    const int own = sf[k][lz + 1][ly + 1];
+    const int up = sf[k - DX[i]][lz + 1 - DZ[i]][ly + 1 - DY[i]];
+    StagedSlot q;
+    q.up_solid = up < 0;
+    q.dir = (!odd || q.up_solid) ? i : opp(i);
+    q.id = (uint32_t)((!odd || q.up_solid) ? own : up);
+    return q;
+}
+
+// Codec reference of a stored value: the densities (previous level) of the
+// node that wrote it, x itself across a wall, else x - e_i.
+struct CodecRef {
+    float rw[2], rt, inv;
+};
+
 template <class C>
-__global__ void k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const uint32_t* __restrict__ nbm,
-                               const float2* __restrict__ psi, const float* __restrict__ held, Geo g, int odd,
-                               float rho_in, float rho_out) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ CodecRef codec_ref(const float2* psi, const Nb& n, int i, bool up_solid) {
+    CodecRef c{{0.f, 0.f}, 0.f, 0.f};
+    if constexpr (C::kRef) {
+        const float2 r = ld(psi, up_solid ? n.idx : n.at(i, -1));
+        c.rw[0] = r.x;
+        c.rw[1] = r.y;
+        c.rt = r.x + r.y;
+        c.inv = inv_total(r);
+    }
+    return c;
+}
+
+// odd: parity of the time level the populations are at (the one just
+// reached); psi: densities of the level before, the codec reference of every
+// value written in the last step.
+template <class C>
+__global__ void __launch_bounds__(OPEN_PATCH * OPEN_PATCH)
+k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict__ psi,
+               const float* __restrict__ held, Geo g, int odd, float rho_in, float rho_out) {
+    using T = typename C::T;
+    using P2 = Pair<T>;
+    __shared__ int sf[OPEN_XS][OPEN_H][OPEN_H];   // [x position][z][y]
+    const int npatch = open_patches(g);
+    const int b = active_of_block(2 * npatch);
+    if (b < 0) return;                             // uniform over the block
+    const int side = b >= npatch ? 1 : 0;
+    const int p = b - side * npatch, pyn = (g.ny + OPEN_PATCH - 1) / OPEN_PATCH;
+    const int y0 = (p % pyn) * OPEN_PATCH, z0 = (p / pyn) * OPEN_PATCH;
+    // staged x positions k = 0..4: x = -1..3 (inlet) or nx-4..nx (outlet), periodic
+    const int xbase = side ? g.nx - 4 : g.nx - 1;
+    for (int e = threadIdx.x; e < OPEN_XS * OPEN_H * OPEN_H; e += blockDim.x) {
+        const int k = e % OPEN_XS, r = e / OPEN_XS;
+        const int hy = r % OPEN_H, hz = r / OPEN_H;
+        const int x = (xbase + k) % g.nx;
+        const int y = (y0 - 1 + hy + g.ny) % g.ny, z = (z0 - 1 + hz + g.nz) % g.nz;
+        sf[k][hz][hy] = fid[(uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z)];
+    }
+    __syncthreads();
+    const int ly = (int)(threadIdx.x % OPEN_PATCH), lz = (int)(threadIdx.x / OPEN_PATCH);
+    const int y = y0 + ly, z = z0 + lz;
+    if (y >= g.ny || z >= g.nz) return;
     const int A = g.ny * g.nz;
-    if (a >= 2 * A) return;
-    const int side = a >= A ? 1 : 0;
-    const int yz = a - side * A;
-    const int y = yz % g.ny, z = yz / g.ny;
-    const int xb = side ? g.nx - 2 : 1, xf = side ? g.nx - 3 : 2, xg = side ? g.nx - 1 : 0;
+    const int yz = y + g.ny * z;
+    const int kf = side ? 1 : 3, kb = 2, kg = side ? 3 : 1;   // staged positions of x_f, x_b, x_g
     const int imposed = side, other = 1 - side, dir_in = side ? -1 : 1;
     const float rho_b = side ? rho_out : rho_in;
     const int np = g.np;
+    const Nb nf(side ? g.nx - 3 : 2, y, z, g), nb(side ? g.nx - 2 : 1, y, z, g), ng(side ? g.nx - 1 : 0, y, z, g);
 
     // populations of x_f at the new level
-    const Nb nf(xf, y, z, g);
-    const uint32_t kf = (uint32_t)fid[nf.idx];
-    const uint32_t mf = nbm[nf.idx];
     float ff[2][Q];
+    {
+        const Pair<float> r = ld(P.rests(), (uint32_t)sf[kf][lz + 1][ly + 1]);
+        ff[0][0] = r.v[0];
+        ff[1][0] = r.v[1];
+    }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        ff[s][0] = *P.rest_at(s, kf);
-#pragma unroll
-        for (int i = 1; i < Q; ++i) ff[s][i] = read_pop<C>(P, s, slot_of(i, odd, kf, mf, nf, fid), i, psi, np);
+    for (int i = 1; i < Q; ++i) {
+        const StagedSlot q = staged_slot(i, odd, kf, ly, lz, sf);
+        const CodecRef c = codec_ref<C>(psi, nf, i, q.up_solid);
+        const P2 h = ld(P.plane(q.dir, np), q.id);
+        ff[0][i] = C::dec(h.v[0], weight(i), c.rw[0], c.rt);
+        ff[1][i] = C::dec(h.v[1], weight(i), c.rw[1], c.rt);
     }
     float rf[2] = {0.f, 0.f}, j[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -135,37 +196,46 @@ __global__ void k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const uin
     const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
     const float usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 
-    // boundary node
-    const Nb nb(xb, y, z, g);
-    const uint32_t kb = (uint32_t)fid[nb.idx];
-    const uint32_t mb = nbm[nb.idx];
+    // boundary node: the imposed component by NEEM; the other component's
+    // entering populations from the held values (both components of those
+    // slots in one store)
+    const uint32_t idb = (uint32_t)sf[kb][lz + 1][ly + 1];
     float moving = 0.f;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
+        const StagedSlot q = staged_slot(i, odd, kb, ly, lz, sf);
+        const CodecRef c = codec_ref<C>(psi, nb, i, q.up_solid);
         const float v = ff[imposed][i] + feq(i, rho_b, u, usq) - feq(i, rf[imposed], u, usq);
-        moving += write_pop<C>(P, imposed, slot_of(i, odd, kb, mb, nb, fid), i, v, psi, np);
-    }
-    *P.rest_at(imposed, kb) = rho_b - moving;  // exact imposed density
-#pragma unroll
-    for (int i = 1; i < Q; ++i)
+        const T hi = C::enc(v, weight(i), c.rw[imposed], c.inv);
+        moving += C::dec(hi, weight(i), c.rw[imposed], c.rt);
         if (DX[i] == dir_in) {
-            const float v = held[((size_t)side * Q + i) * A + yz];
-            write_pop<C>(P, other, slot_of(i, odd, kb, mb, nb, fid), i, v, psi, np);
+            const float vo = held[((size_t)side * Q + i) * A + yz];
+            const T ho = C::enc(vo, weight(i), c.rw[other], c.inv);
+            P2 pr;
+            pr.v[imposed] = hi;
+            pr.v[other] = ho;
+            st(P.plane(q.dir, np), q.id, pr);
+        } else {
+            *P.at(imposed, q.dir, q.id, np) = hi;
         }
+    }
+    *P.rest_at(imposed, idb) = rho_b - moving;   // exact imposed density
 
     // ghost node: rest equilibrium at its (mirrored) densities
-    const Nb ng(xg, y, z, g);
-    const uint32_t kg = (uint32_t)fid[ng.idx];
-    const uint32_t mg = nbm[ng.idx];
     const float2 rg = psi[ng.idx];
+    float sum[2] = {0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const float r = s ? rg.y : rg.x;
-        float sum = 0.f;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) sum += write_pop<C>(P, s, slot_of(i, odd, kg, mg, ng, fid), i, weight(i) * r, psi, np);
-        *P.rest_at(s, kg) = r - sum;
+    for (int i = 1; i < Q; ++i) {
+        const StagedSlot q = staged_slot(i, odd, kg, ly, lz, sf);
+        const CodecRef c = codec_ref<C>(psi, ng, i, q.up_solid);
+        P2 pr;
+        pr.v[0] = C::enc(weight(i) * rg.x, weight(i), c.rw[0], c.inv);
+        pr.v[1] = C::enc(weight(i) * rg.y, weight(i), c.rw[1], c.inv);
+        sum[0] += C::dec(pr.v[0], weight(i), c.rw[0], c.rt);
+        sum[1] += C::dec(pr.v[1], weight(i), c.rw[1], c.rt);
+        st(P.plane(q.dir, np), q.id, pr);
     }
+    st(P.rests(), (uint32_t)sf[kg][lz + 1][ly + 1], Pair<float>{{rg.x - sum[0], rg.y - sum[1]}});
 }
 
 // Mean pressure (Eq. 12) over the fluid nodes of the inlet (x = 1) and outlet
@@ -245,10 +315,10 @@ void launch_open_mirror(float2* psi, const Geo& g, hipStream_t s) {
 }
 
 template <class C>
-void launch_open_rebuild(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* psi, const float* held,
-                         const Geo& g, int odd, float rho_in, float rho_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_open_rebuild<C>, dim3(blocks_for(2 * g.ny * g.nz, 64)), dim3(64), 0, s, P, fid, nbm, psi,
-                       held, g, odd, rho_in, rho_out);
+void launch_open_rebuild(const Pops<C>& P, const int* fid, const float2* psi, const float* held, const Geo& g,
+                         int odd, float rho_in, float rho_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_open_rebuild<C>, dim3(xcd_grid(2 * open_patches(g))), dim3(OPEN_PATCH * OPEN_PATCH), 0, s,
+                       P, fid, psi, held, g, odd, rho_in, rho_out);
 }
 
 template <class C>
@@ -268,8 +338,8 @@ void launch_open_check(const uint32_t* nbm, const Geo& g, int* count, hipStream_
 }
 
 #define MCLBM_OPEN_INSTANTIATE(C)                                                                              \
-    template void launch_open_rebuild<C>(const Pops<C>&, const int*, const uint32_t*, const float2*,         \
-                                         const float*, const Geo&, int, float, float, hipStream_t);          \
+    template void launch_open_rebuild<C>(const Pops<C>&, const int*, const float2*, const float*, const Geo&, \
+                                         int, float, float, hipStream_t);                                    \
     template void launch_open_capture<C>(const Pops<C>&, const int*, const uint32_t*, const float2*, float*, \
                                          const Geo&, int, hipStream_t);
 MCLBM_OPEN_INSTANTIATE(CodecF32)

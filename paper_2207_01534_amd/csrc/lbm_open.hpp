@@ -11,8 +11,8 @@ void launch_open_mirror(float2* psi, const Geo& g, hipStream_t s);
 // Boundary rebuild at the level of parity odd; psi holds the densities of the
 // level before (codec references); held: [2][19][ny*nz] FP32.
 template <class C>
-void launch_open_rebuild(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* psi, const float* held,
-                         const Geo& g, int odd, float rho_in, float rho_out, hipStream_t s);
+void launch_open_rebuild(const Pops<C>& P, const int* fid, const float2* psi, const float* held, const Geo& g,
+                         int odd, float rho_in, float rho_out, hipStream_t s);
 // Capture the held populations from the state at the level of parity odd
 // (rprev: the codec references of that level).
 template <class C>

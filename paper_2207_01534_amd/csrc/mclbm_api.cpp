@@ -328,7 +328,7 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
                                      lat->ph, odd, lat->stream);
             mark(2);
             if (lat->open)
-                launch_open_rebuild<C>(lat->pops<C>(), lat->fid(), lat->nbm(), psi, lat->held(), lat->g, 1 - odd,
+                launch_open_rebuild<C>(lat->pops<C>(), lat->fid(), psi, lat->held(), lat->g, 1 - odd,
                                        lat->rho_in, lat->rho_out, lat->stream);
         });
         lat->t += 1;
