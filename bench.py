@@ -199,8 +199,32 @@ def cpu_baseline(w, target_s):
     o.run(k)
     dt = time.perf_counter() - t0
     n = sx * sy * sz
-    return {"value": n * k / dt / 1e6, "unit": "MLUPS", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{sx}x{sy}x{sz} sub-block of {w.name} (periodic), {k} FP64 steps in {dt:.1f} s"}
+    cores = orc.num_threads()
+    # per-core rate: the same sub-block on one thread, a few seconds of work
+    orc.set_num_threads(1)
+    t0 = time.perf_counter()
+    o.run(1)
+    one1 = time.perf_counter() - t0
+    k1 = max(1, min(k, int(target_s / 4.0 / max(one1, 1e-3))))
+    t0 = time.perf_counter()
+    o.run(k1)
+    dt1 = time.perf_counter() - t0
+    orc.set_num_threads(cores)
+    return {"value": n * k / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{sx}x{sy}x{sz} sub-block of {w.name} (periodic), {k} FP64 steps in {dt:.1f} s",
+            "one_core_value": n * k1 / dt1 / 1e6,
+            "one_core_sample": f"same sub-block on 1 thread, {k1} steps in {dt1:.1f} s",
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def calibrate_copy():

@@ -63,6 +63,7 @@ def _lib():
         lib.orc_loss_snw.argtypes = [P, bp, bp, dp]
         lib.orc_loss_snw.restype = ctypes.c_double
         lib.orc_num_threads.restype = ctypes.c_int32
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int32]
         lib.orc_open_rebuild.argtypes = [P, bp, dp]
         _LIB = lib
     return _LIB
@@ -80,6 +81,11 @@ def _b(a):
 
 def num_threads() -> int:
     return int(_lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the lattice-wide loops from now on."""
+    _lib().orc_set_num_threads(int(n))
 
 
 def lattice_tables():

@@ -39,6 +39,7 @@ def test_bench_prints_one_complete_json_line(monkeypatch, capsys):
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], rel=1e-3)
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
+    assert cb["one_core_value"] > 0 and "cpu_model" in cb
     assert set(d["variants"]) == {"f16", "bf16"}
 
 
