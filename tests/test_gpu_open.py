@@ -44,6 +44,33 @@ def _case(nxp=22, ny=12, nz=10, seed=7):
     return (nxp + 2, ny, nz), g_solid, g_xi, g_rho, (nxp, ny, nz), solid, xi, rho
 
 
+def _case_ragged(nxp=20, ny=37, nz=21, seed=11):
+    """Boundary planes wider than one 16 x 16 patch of rows in y and z, with a
+    ragged last patch in both, and grains that reach the plane next to the
+    boundary plane (physical x = 2 and nxp - 3), so that the rebuild meets
+    wall slots there; otherwise as _case."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nxp)[None, None, :]
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nxp), indexing="ij")
+    solid = np.zeros((nz, ny, nxp), np.uint8)
+    for cx in (4.5, nxp - 5.5, 4.5, nxp - 5.5, nxp / 2.0):
+        cy, cz = rng.uniform(0, ny), rng.uniform(0, nz)
+        dy = (yy - cy + ny / 2.0) % ny - ny / 2.0             # periodic in y and z
+        dz = (zz - cz + nz / 2.0) % nz - nz / 2.0
+        solid[(xx - cx) ** 2 + dy ** 2 + dz ** 2 <= 2.6 ** 2] = 1
+    solid[:, :, :2] = 0
+    solid[:, :, nxp - 2:] = 0
+    assert solid[:, :, 2].any() and solid[:, :, nxp - 3].any()
+    phi = 0.5 * (1.0 + np.tanh((5.0 - x) / 2.5)) * np.ones((nz, ny, nxp))
+    r1 = 0.03 + (1.0 - 0.03) * phi
+    r2 = 0.03 + (1.0 - 0.03) * (1.0 - phi)
+    rho = np.stack([r1, r2]).astype(np.float32)
+    xi = np.where(solid != 0, -0.2, 0.0).astype(np.float32)
+    pad = lambda a: np.concatenate([a[..., :1], a, a[..., -1:]], axis=-1)
+    return ((nxp + 2, ny, nz), pad(solid), pad(xi), np.stack([pad(rho[0]), pad(rho[1])]),
+            (nxp, ny, nz), solid, xi, rho)
+
+
 def _oracle(shape, solid, xi, rho):
     o = Oracle(OracleParams(shape, tau=TAU, G=G), solid, xi.astype(np.float64))
     r = rho.astype(np.float64)
@@ -86,6 +113,27 @@ def test_open_planes_match_oracle_with_inlet_ramp(storage, e_rho_bar, e_u_bar):
     r = lat.density().cpu().numpy()
     np.testing.assert_allclose(r[0][:, :, 1], RHO_IN + 0.02, rtol=0, atol=2e-6)
     np.testing.assert_allclose(r[1][:, :, -2], RHO_OUT, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("storage,e_rho_bar,e_u_bar", [(0, 1e-5, 1e-4), (1, 2e-3, 2e-3)], ids=["f32", "f16"])
+def test_open_planes_over_several_ragged_row_patches(storage, e_rho_bar, e_u_bar):
+    gshape, gsolid, gxi, grho, oshape, osolid, oxi, orho = _case_ragged()
+    print(f"[case] open planes ragged {oshape} (+2 ghost planes) storage={storage}", flush=True)
+    lat = gpu_case(gshape, gsolid, gxi, grho, TAU, G, ((0, 0, 0), (0, 0, 0)), storage=storage)
+    o = _oracle(oshape, osolid, oxi, orho)
+    lat.set_open_x(RHO_IN, RHO_OUT)
+    o.set_open_x(RHO_IN, RHO_OUT)
+    lat.step(101)                                            # ends on an odd level
+    o.run(101)
+    e = field_errors(_interior(gpu_fields(lat)), _oracle_fields(o), osolid)
+    print(f"[open] ragged storage={storage} e_rho={e['e_rho']:.3e} e_u={e['e_u']:.3e} e_F={e['e_F']:.3e} "
+          f"u_max={e['u_max']:.3e}", flush=True)
+    assert e["u_max"] > 1e-4
+    assert e["e_rho"] <= e_rho_bar and e["e_u"] <= e_u_bar, e
+    r = lat.density().cpu().numpy()
+    fl_in, fl_out = gsolid[:, :, 1] == 0, gsolid[:, :, -2] == 0
+    np.testing.assert_allclose(r[0][:, :, 1][fl_in], RHO_IN, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(r[1][:, :, -2][fl_out], RHO_OUT, rtol=0, atol=2e-6)
 
 
 def test_open_pressure_readout_matches_oracle():
