@@ -41,16 +41,27 @@ OPEN_MUTANTS = [
      "                        j[1] += EX[i] * fi;"),
 ]
 
+# planted mistakes in the smooth non-wetting saturation (the adjoint's loss)
+LOSS_MUTANTS = [
+    ("loss_skips_rest_population", "for (int i = 0; i < Q; ++i) r[s] += f[((size_t)s * Q + i) * N + n];",
+     "for (int i = 1; i < Q; ++i) r[s] += f[((size_t)s * Q + i) * N + n];"),
+    ("loss_wrong_component", "acc += r[0] / (r[0] + r[1]);", "acc += r[1] / (r[0] + r[1]);"),
+    ("loss_counts_solid", "if (solid[n] || !region[n]) continue;", "if (!region[n]) continue;"),
+    ("loss_ignores_region", "if (solid[n] || !region[n]) continue;", "if (solid[n]) continue;"),
+]
+
 PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
              os.path.join(ROOT, "tests", "test_oracle_physics.py") + "::test_single_fluid_poiseuille"]
 
 
 OPEN_PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_open.py")]
+LOSS_PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_loss.py")]
 
 
 @pytest.mark.parametrize("name,orig,planted,pins",
-                         [m + (PIN_TESTS,) for m in MUTANTS] + [m + (OPEN_PIN_TESTS,) for m in OPEN_MUTANTS],
-                         ids=[m[0] for m in MUTANTS + OPEN_MUTANTS])
+                         [m + (PIN_TESTS,) for m in MUTANTS] + [m + (OPEN_PIN_TESTS,) for m in OPEN_MUTANTS]
+                         + [m + (LOSS_PIN_TESTS,) for m in LOSS_MUTANTS],
+                         ids=[m[0] for m in MUTANTS + OPEN_MUTANTS + LOSS_MUTANTS])
 def test_planted_mistake_is_caught(name, orig, planted, pins, tmp_path):
     src = open(SRC).read()
     assert src.count(orig) == 1, name
