@@ -120,6 +120,47 @@ def gaussian_field_medium(shape, ell, porosity, seed, buffer=3):
     return solid, info
 
 
+def percolating_fraction(solid, buffer=3):
+    """Fraction of the sample's pore voxels (x in [buffer, nx - buffer)) that
+    belong to a pore cluster joining the inlet buffer (x < buffer) to the
+    outlet buffer (x >= nx - buffer) through the sample.  Two pore voxels are
+    connected when they are D3Q19 neighbours (sharing a face or an edge);
+    the lattice is periodic in y and z, not in x."""
+    from scipy import ndimage
+    nz, ny, nx = solid.shape
+    pore = np.pad(solid == 0, ((1, 1), (1, 1), (0, 0)), mode="wrap")   # one periodic copy layer in z, y
+    lab, n = ndimage.label(pore, structure=ndimage.generate_binary_structure(3, 2))
+    parent = np.arange(n + 1)
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    # a copy-layer voxel is the same voxel as its periodic original: join their clusters
+    core = lab[1:-1, 1:-1, :]
+    pairs = [(lab[0, 1:-1, :], core[-1]), (lab[-1, 1:-1, :], core[0]),
+             (lab[1:-1, 0, :], core[:, -1]), (lab[1:-1, -1, :], core[:, 0])]
+    zy = [(0, 0, -1, -1), (0, -1, -1, 0), (-1, 0, 0, -1), (-1, -1, 0, 0)]   # the four copied edges
+    pairs += [(lab[a, b, :], core[c, d]) for a, b, c, d in zy]
+    for u, v in pairs:
+        m = (u > 0) & (v > 0)
+        for a, b in np.unique(np.stack([u[m], v[m]], axis=1), axis=0):
+            ra, rb = find(a), find(b)
+            if ra != rb:
+                parent[ra] = rb
+    roots = np.array([find(a) for a in range(n + 1)])
+    root = roots[core]
+    inlet = set(np.unique(root[:, :, :buffer][core[:, :, :buffer] > 0]).tolist())
+    outlet = set(np.unique(root[:, :, nx - buffer:][core[:, :, nx - buffer:] > 0]).tolist())
+    spanning = np.array(sorted(inlet & outlet), dtype=root.dtype)
+    sample = core[:, :, buffer:nx - buffer] > 0
+    if not sample.any():
+        return 0.0
+    return float(np.isin(root[:, :, buffer:nx - buffer][sample], spanning).mean())
+
+
 def uniform_xi(solid, lo, hi, seed):
     """Per-voxel adhesion parameter, i.i.d. U[lo, hi] at solid voxels, 0 elsewhere (float32)."""
     rng = _rng(seed)
