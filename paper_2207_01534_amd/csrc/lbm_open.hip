@@ -83,8 +83,10 @@ __global__ void k_open_mirror(float2* __restrict__ psi, Geo g) {
 // boundary, next inwards) sit in consecutive slots of every direction plane,
 // and at odd levels their slots are addressed through the fluid ids of the
 // rows next to it; the block stages those ids once in LDS (five x positions
-// over the patch and a one-row halo in y and z), and every slot moves both
-// components in one access where both are read or written.
+// over the patch and a one-row halo in y and z), with the F16/BF16 codecs
+// also the previous-level densities that decode and encode each slot, and
+// every slot moves both components in one access where both are read or
+// written.
 constexpr int OPEN_PATCH = 16;
 constexpr int OPEN_XS = 5, OPEN_H = OPEN_PATCH + 2;
 
@@ -112,16 +114,17 @@ __device__ __forceinline__ StagedSlot staged_slot(int i, bool odd, int k, int ly
 }
 
 // Codec reference of a stored value: the densities (previous level) of the
-// node that wrote it, x itself across a wall, else x - e_i.
+// node that wrote it, x itself across a wall, else x - e_i; read from the
+// block's staged copy (F16/BF16 only).
 struct CodecRef {
     float rw[2], rt, inv;
 };
 
-template <class C>
-__device__ __forceinline__ CodecRef codec_ref(const float2* psi, const Nb& n, int i, bool up_solid) {
+template <class C, class Staged>
+__device__ __forceinline__ CodecRef codec_ref(const Staged& sr, int k, int ly, int lz, int i, bool up_solid) {
     CodecRef c{{0.f, 0.f}, 0.f, 0.f};
     if constexpr (C::kRef) {
-        const float2 r = ld(psi, up_solid ? n.idx : n.at(i, -1));
+        const float2 r = up_solid ? sr[k][lz + 1][ly + 1] : sr[k - DX[i]][lz + 1 - DZ[i]][ly + 1 - DY[i]];
         c.rw[0] = r.x;
         c.rw[1] = r.y;
         c.rt = r.x + r.y;
@@ -140,6 +143,7 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
     using T = typename C::T;
     using P2 = Pair<T>;
     __shared__ int sf[OPEN_XS][OPEN_H][OPEN_H];   // [x position][z][y]
+    __shared__ float2 sr[C::kRef ? OPEN_XS : 1][OPEN_H][OPEN_H];   // codec references, same positions
     const int npatch = open_patches(g);
     const int b = active_of_block(2 * npatch);
     if (b < 0) return;                             // uniform over the block
@@ -153,7 +157,9 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
         const int hy = r % OPEN_H, hz = r / OPEN_H;
         const int x = (xbase + k) % g.nx;
         const int y = (y0 - 1 + hy + g.ny) % g.ny, z = (z0 - 1 + hz + g.nz) % g.nz;
-        sf[k][hz][hy] = fid[(uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z)];
+        const uint32_t idx = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+        sf[k][hz][hy] = fid[idx];
+        if constexpr (C::kRef) sr[k][hz][hy] = ld(psi, idx);
     }
     __syncthreads();
     const int ly = (int)(threadIdx.x % OPEN_PATCH), lz = (int)(threadIdx.x / OPEN_PATCH);
@@ -165,7 +171,7 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
     const int imposed = side, other = 1 - side, dir_in = side ? -1 : 1;
     const float rho_b = side ? rho_out : rho_in;
     const int np = g.np;
-    const Nb nf(side ? g.nx - 3 : 2, y, z, g), nb(side ? g.nx - 2 : 1, y, z, g), ng(side ? g.nx - 1 : 0, y, z, g);
+    const Nb ng(side ? g.nx - 1 : 0, y, z, g);
 
     // populations of x_f at the new level
     float ff[2][Q];
@@ -177,7 +183,7 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const StagedSlot q = staged_slot(i, odd, kf, ly, lz, sf);
-        const CodecRef c = codec_ref<C>(psi, nf, i, q.up_solid);
+        const CodecRef c = codec_ref<C>(sr, kf, ly, lz, i, q.up_solid);
         const P2 h = ld(P.plane(q.dir, np), q.id);
         ff[0][i] = C::dec(h.v[0], weight(i), c.rw[0], c.rt);
         ff[1][i] = C::dec(h.v[1], weight(i), c.rw[1], c.rt);
@@ -204,7 +210,7 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const StagedSlot q = staged_slot(i, odd, kb, ly, lz, sf);
-        const CodecRef c = codec_ref<C>(psi, nb, i, q.up_solid);
+        const CodecRef c = codec_ref<C>(sr, kb, ly, lz, i, q.up_solid);
         const float v = ff[imposed][i] + feq(i, rho_b, u, usq) - feq(i, rf[imposed], u, usq);
         const T hi = C::enc(v, weight(i), c.rw[imposed], c.inv);
         moving += C::dec(hi, weight(i), c.rw[imposed], c.rt);
@@ -227,7 +233,7 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const StagedSlot q = staged_slot(i, odd, kg, ly, lz, sf);
-        const CodecRef c = codec_ref<C>(psi, ng, i, q.up_solid);
+        const CodecRef c = codec_ref<C>(sr, kg, ly, lz, i, q.up_solid);
         P2 pr;
         pr.v[0] = C::enc(weight(i) * rg.x, weight(i), c.rw[0], c.inv);
         pr.v[1] = C::enc(weight(i) * rg.y, weight(i), c.rw[1], c.inv);
