@@ -125,3 +125,34 @@ def test_fluid_capacity_enforced_and_used():
     with pytest.raises(MclbmError):
         Lattice(LatticeParams(shape=w.shape, tau=w.tau, G=w.G, g=w.g, fluid_capacity=nf - 1),
                 torch.as_tensor(w.solid), torch.as_tensor(w.xi))
+
+
+def test_xi_out_of_range_refused_only_where_it_is_read():
+    """chi = 1 +- xi (Eqs. 14-15 and the rule after them) must stay positive:
+    |xi| >= 1 at a solid voxel with a fluid neighbour is refused and leaves
+    the lattice without geometry; at a solid voxel deep inside a grain xi is
+    never read and any value is accepted; a valid geometry afterwards restores
+    a working lattice."""
+    import torch
+    from paper_2207_01534_amd.lattice import MclbmError
+    shape = (24, 16, 12)
+    nz, ny, nx = shape[::-1]
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[3:9, 4:12, 6:16] = 1                         # a block: interior voxels have no fluid neighbour
+    rho = wl.tanh_droplet(shape, 4.0)
+    rho[:, solid != 0] = 0
+    xi = np.where(solid != 0, 0.2, 0.0).astype(np.float32)
+    lat = gpu_case(shape, solid, xi, rho, (1.0, 1.0), 3.5, ((0, 0, 0), (0, 0, 0)))
+    deep = xi.copy()
+    deep[5, 7, 10] = 1.5                               # inside the block
+    lat.set_geometry(torch.as_tensor(solid), torch.as_tensor(deep))
+    face = xi.copy()
+    face[3, 7, 10] = 1.0                               # on the block's face (fluid at z = 2)
+    with pytest.raises(MclbmError):
+        lat.set_geometry(torch.as_tensor(solid), torch.as_tensor(face))
+    with pytest.raises(MclbmError):
+        lat.fluid_count()                              # no geometry after the refusal
+    lat.set_geometry(torch.as_tensor(solid), torch.as_tensor(xi))
+    lat.init_equilibrium(torch.as_tensor(rho.astype(np.float32)))
+    lat.step(4)
+    assert lat.time == 4 and lat.diagnostics()["nonfinite"] == 0
