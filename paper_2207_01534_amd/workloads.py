@@ -120,16 +120,13 @@ def gaussian_field_medium(shape, ell, porosity, seed, buffer=3):
     return solid, info
 
 
-def percolating_fraction(solid, buffer=3):
-    """Fraction of the sample's pore voxels (x in [buffer, nx - buffer)) that
-    belong to a pore cluster joining the inlet buffer (x < buffer) to the
-    outlet buffer (x >= nx - buffer) through the sample.  Two pore voxels are
-    connected when they are D3Q19 neighbours (sharing a face or an edge);
-    the lattice is periodic in y and z, not in x."""
+def _clusters(mask):
+    """Cluster ids of a boolean mask (nz, ny, nx): voxels are connected when
+    they are D3Q19 neighbours (sharing a face or an edge), periodically in y
+    and z, not in x.  Returns an int array, 0 outside the mask."""
     from scipy import ndimage
-    nz, ny, nx = solid.shape
-    pore = np.pad(solid == 0, ((1, 1), (1, 1), (0, 0)), mode="wrap")   # one periodic copy layer in z, y
-    lab, n = ndimage.label(pore, structure=ndimage.generate_binary_structure(3, 2))
+    m = np.pad(mask, ((1, 1), (1, 1), (0, 0)), mode="wrap")          # one periodic copy layer in z, y
+    lab, n = ndimage.label(m, structure=ndimage.generate_binary_structure(3, 2))
     parent = np.arange(n + 1)
 
     def find(a):
@@ -145,20 +142,65 @@ def percolating_fraction(solid, buffer=3):
     zy = [(0, 0, -1, -1), (0, -1, -1, 0), (-1, 0, 0, -1), (-1, -1, 0, 0)]   # the four copied edges
     pairs += [(lab[a, b, :], core[c, d]) for a, b, c, d in zy]
     for u, v in pairs:
-        m = (u > 0) & (v > 0)
-        for a, b in np.unique(np.stack([u[m], v[m]], axis=1), axis=0):
+        both = (u > 0) & (v > 0)
+        for a, b in np.unique(np.stack([u[both], v[both]], axis=1), axis=0):
             ra, rb = find(a), find(b)
             if ra != rb:
                 parent[ra] = rb
     roots = np.array([find(a) for a in range(n + 1)])
-    root = roots[core]
-    inlet = set(np.unique(root[:, :, :buffer][core[:, :, :buffer] > 0]).tolist())
-    outlet = set(np.unique(root[:, :, nx - buffer:][core[:, :, nx - buffer:] > 0]).tolist())
-    spanning = np.array(sorted(inlet & outlet), dtype=root.dtype)
-    sample = core[:, :, buffer:nx - buffer] > 0
+    return roots[core]
+
+
+def percolating_fraction(solid, buffer=3):
+    """Fraction of the sample's pore voxels (x in [buffer, nx - buffer)) that
+    belong to a pore cluster joining the inlet buffer (x < buffer) to the
+    outlet buffer (x >= nx - buffer) through the sample (clusters as in
+    _clusters)."""
+    nx = solid.shape[2]
+    pore = solid == 0
+    root = _clusters(pore)
+    inlet = np.unique(root[:, :, :buffer][pore[:, :, :buffer]])
+    outlet = np.unique(root[:, :, nx - buffer:][pore[:, :, nx - buffer:]])
+    spanning = np.intersect1d(inlet, outlet)
+    sample = pore[:, :, buffer:nx - buffer]
     if not sample.any():
         return 0.0
     return float(np.isin(root[:, :, buffer:nx - buffer][sample], spanning).mean())
+
+
+def trapped_region(rho, solid, buffer=3):
+    """Trapped non-wetting phase: fluid voxels where component 1 dominates
+    (rho1 > rho2) that belong to a component-1 cluster (as in _clusters) not
+    reaching the inlet buffer (x < buffer).  Returns a uint8 mask, the frozen
+    region of the trapped-saturation loss."""
+    nw = (solid == 0) & (np.asarray(rho[0]) > np.asarray(rho[1]))
+    root = _clusters(nw)
+    inlet = np.unique(root[:, :, :buffer][nw[:, :, :buffer]])
+    return (nw & ~np.isin(root, inlet)).astype(np.uint8)
+
+
+def ganglia_rho(solid, n_blobs, radius, seed, buffer=3, width=2.5):
+    """Component 1 (non-wetting) as dispersed blobs of the given radius centred
+    at seeded random pore voxels, plus the inlet buffer; component 2 elsewhere.
+    Each blob and the reservoir carry a tanh interface of the given width;
+    densities RHO_MAJOR / RHO_MINOR, 0 at solid voxels."""
+    nz, ny, nx = solid.shape
+    rng = _rng(seed)
+    pores = np.argwhere(solid[:, :, buffer + int(radius):nx - buffer - int(radius)] == 0)
+    pick = pores[rng.choice(len(pores), size=n_blobs, replace=False)]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = 0.5 * (1.0 + np.tanh(2.0 * (buffer - 0.5 - x) / width))          # inlet reservoir
+    for cz, cy, cx in pick:
+        cx = cx + buffer + int(radius)
+        dz = (z - cz + nz / 2.0) % nz - nz / 2.0
+        dy = (y - cy + ny / 2.0) % ny - ny / 2.0
+        d = np.sqrt((x - cx) ** 2 + dy ** 2 + dz ** 2)
+        phi = np.maximum(phi, 0.5 * (1.0 - np.tanh(2.0 * (d - radius) / width)))
+    r1 = RHO_MINOR + (RHO_MAJOR - RHO_MINOR) * phi
+    r2 = RHO_MINOR + (RHO_MAJOR - RHO_MINOR) * (1.0 - phi)
+    rho = np.stack([r1, r2])
+    rho[:, solid != 0] = 0.0
+    return rho
 
 
 def uniform_xi(solid, lo, hi, seed):

@@ -1,6 +1,7 @@
 """Hand-written adjoint (HIP, FP32) against central finite differences of the
-FP64 oracle, for the smooth non-wetting saturation loss with respect to the
-per-voxel adhesion parameter xi.  Bar: |g_adj - g_fd| <= 1e-3 max |g_fd|."""
+FP64 oracle, for the smooth non-wetting saturation loss (over the sample, or
+over the trapped ganglia) and the outlet flux, with respect to the per-voxel
+adhesion parameter xi.  Bar: |g_adj - g_fd| <= 1e-3 max |g_fd|."""
 import json
 import os
 
@@ -93,6 +94,52 @@ def test_small_gradient_against_oracle_fd(steps, every):
     # by the O(eps^2) truncation term only
     assert dd_half == pytest.approx(dd, rel=1e-5, abs=1e-6 * scale)
     assert float((grad * v).sum()) == pytest.approx(dd_half, rel=1e-3, abs=1e-3 * scale)
+
+
+def test_trapped_saturation_gradient_against_oracle_fd():
+    """The trapped variant of the loss: the smooth non-wetting saturation over
+    the non-wetting ganglia cut off from the inlet reservoir in the
+    unperturbed run at T (found on the oracle's own run, then frozen), on a
+    porous lattice seeded with dispersed ganglia."""
+    shape, steps, every = (20, 14, 12), 30, 7
+    print(f"[case] adjoint trapped {shape} steps={steps} every={every}", flush=True)
+    solid, _ = wl.sphere_pack(shape, 2.0, 0.6, seed=91)
+    rho = wl.ganglia_rho(solid, 4, 2.0, seed=92)
+    xi = wl.uniform_xi(solid, -0.4, 0.4, seed=93)
+    tau, G, g = (1.5, 0.6), 3.5, ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    xi64 = xi.astype(np.float64)
+    o = Oracle(OracleParams(shape, tau=tau, G=G, g=g), solid, xi64)
+    o.init_equilibrium(rho.astype(np.float32).astype(np.float64))
+    o.run(steps)
+    region = wl.trapped_region(o.fields()[0], solid)
+    assert region.sum() > 50
+    L_orc = o.loss_snw(region)
+    L_gpu, grad, _ = _gpu_gradient(shape, solid, xi, rho, tau, G, g, steps, every, region)
+    assert L_gpu == pytest.approx(L_orc, rel=1e-5, abs=1e-7)
+    bs = _boundary_solid(solid)
+    rng = np.random.default_rng(94)
+    cand = np.argwhere(bs)
+    pick = cand[rng.choice(len(cand), size=10, replace=False)]
+    eps = 1e-3
+    fd = []
+    for z, y, x in pick:
+        xp, xm = xi64.copy(), xi64.copy()
+        xp[z, y, x] += eps
+        xm[z, y, x] -= eps
+        fd.append((_oracle_loss(shape, solid, xp, rho, tau, G, g, steps, region)
+                   - _oracle_loss(shape, solid, xm, rho, tau, G, g, steps, region)) / (2 * eps))
+    fd = np.array(fd)
+    adj = np.array([grad[z, y, x] for z, y, x in pick])
+    scale = np.abs(fd).max()
+    err = np.abs(adj - fd).max() / scale
+    print(f"[adjoint-trapped] region={int(region.sum())} L={L_gpu:.6f} max|fd|={scale:.3e} rel err={err:.3e}",
+          flush=True)
+    assert scale > 0 and err <= 1e-3
+    v = np.where(bs, rng.standard_normal(bs.shape), 0.0)
+    v /= np.abs(v).max()
+    dd = (_oracle_loss(shape, solid, xi64 + eps * v, rho, tau, G, g, steps, region)
+          - _oracle_loss(shape, solid, xi64 - eps * v, rho, tau, G, g, steps, region)) / (2 * eps)
+    assert float((grad * v).sum()) == pytest.approx(dd, rel=1e-3, abs=1e-3 * scale)
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden finite differences not generated")
