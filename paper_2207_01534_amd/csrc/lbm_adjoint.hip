@@ -231,7 +231,6 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const int* __restr
     const int z = blockIdx.z;
     if (x >= g.nx || y >= g.ny) return;
     const Nb nb(x, y, z, g);
-    const size_t n = (size_t)g.n;
     const uint32_t m = nbm[nb.idx];
     if (m & SELF_SOLID) return;
     const uint32_t kf = (uint32_t)fid[nb.idx];
