@@ -147,7 +147,8 @@ def run_adjoint(steps=500, every=25):
     ck = forward_checkpointed()
     lat.gradient_snw(steps, every, ck, reg)
     _, t_fwd = median_of(forward)
-    ck, t_fwd_ck = median_of(forward_checkpointed)
+    _, t_fwd_ck = median_of(forward_checkpointed)
+    ck = forward_checkpointed()  # the reverse sweep differentiates the latest recording
     grad, t_bwd = median_of(lambda: lat.gradient_snw(steps, every, ck, reg))
     return {"workload": "adjoint64: 64^3 sphere pack r=6, porosity 0.40, xi~U[-0.4,0.4]",
             "steps": steps, "every": every, "forward_ms": t_fwd * 1e3,
@@ -157,8 +158,11 @@ def run_adjoint(steps=500, every=25):
             "grad_abs_max": float(grad.abs().max())}
 
 
+# everything that decides what the step kernels touch: the kernels, their
+# launchers and the workspace layout (plane stride, skew) set by the C ABI
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2207_01534_amd", "csrc", f)
-                  for f in ("lbm_device.hpp", "lbm_tiles.hpp", "lbm_kernels.hip")]
+                  for f in ("lbm_device.hpp", "lbm_tiles.hpp", "lbm_kernels.hpp", "lbm_kernels.hip",
+                            "mclbm_api.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_step_kernels.json")
 CODEC = {"f32": "CodecF32", "f16": "CodecF16", "bf16": "CodecBF16"}
 
@@ -182,7 +186,9 @@ def measured_traffic(workload_name, storage):
 
 def cpu_baseline(w, target_s):
     """FP64 oracle on a bounded sub-block of the workload (periodic sub-lattice)."""
-    os.environ.setdefault("OMP_NUM_THREADS", str(min(16, len(os.sched_getaffinity(0)))))
+    # every CPU this process may run on, unless the environment already fixes
+    # the OpenMP thread count (a machine's CPU share per GPU)
+    os.environ.setdefault("OMP_NUM_THREADS", str(len(os.sched_getaffinity(0))))
     from oracle import oracle as orc
     nx, ny, nz = w.shape
     sx, sy, sz = min(nx, 256), min(ny, 128), min(nz, 128)
@@ -214,17 +220,28 @@ def cpu_baseline(w, target_s):
             "sample": f"{sx}x{sy}x{sz} sub-block of {w.name} (periodic), {k} FP64 steps in {dt:.1f} s",
             "one_core_value": n * k1 / dt1 / 1e6,
             "one_core_sample": f"same sub-block on 1 thread, {k1} steps in {dt1:.1f} s",
-            "cpu_model": _cpu_model()}
+            "cpu_model": _cpu_model(), "visible_cpus": len(os.sched_getaffinity(0)),
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
 
 
 def _cpu_model():
+    """The model string of /proc/cpuinfo with its family/model/stepping numbers
+    (a virtual machine may report only a short model name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (t.strip() for t in line.split(":", 1))
+                if k in ("model name", "vendor_id", "cpu family", "model", "stepping", "cpu MHz") and k not in info:
+                    info[k] = v
+            if not line.strip() and info:
+                break
     except OSError:
-        pass
-    return None
+        return None
+    if not info:
+        return None
+    return (f"{info.get('model name', '?')} ({info.get('vendor_id', '?')}, family {info.get('cpu family', '?')}, "
+            f"model {info.get('model', '?')}, stepping {info.get('stepping', '?')}, {info.get('cpu MHz', '?')} MHz)")
 
 
 def calibrate_copy():

@@ -36,7 +36,7 @@
  * overlap from several threads.
  *
  * Errors: every call returns an mclbm_status.  MCLBM_EINVAL leaves the
- * handle unchanged.  HIP failures return MCLBM_EHIP; mclbm_last_error()
+ * handle, its geometry and its state unchanged.  HIP failures return MCLBM_EHIP; mclbm_last_error()
  * gives a thread-local description of the most recent failure.
  */
 #ifndef MCLBM_H
@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define MCLBM_ABI_VERSION 1u
+#define MCLBM_ABI_VERSION 2u
 
 typedef enum {
     MCLBM_OK = 0,
@@ -108,9 +108,13 @@ mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t 
  * Both are copied into the workspace; the caller may free them afterwards.
  * Builds the sparse storage: populations live only at fluid voxels,
  * compacted within tiles of 64 x 4 x 2 voxels; tiles without fluid are
- * dropped.  Synchronises the stream.  Resets the step counter to
- * 0.  On EINVAL (|xi| >= 1, or more fluid voxels than fluid_capacity) the
- * lattice is left without geometry and set_geometry must be called again. */
+ * dropped.  Synchronises the stream.
+ * The candidate geometry is checked before anything is replaced: on EINVAL
+ * (|xi| >= 1 where it is read, or more fluid voxels than fluid_capacity) the
+ * lattice keeps its previous geometry, state, step counter and open planes,
+ * and can go on stepping.  On success the step counter is reset to 0, the
+ * state must be initialised again (init_equilibrium or load_state) and x is
+ * periodic again (open planes off). */
 mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, const float* d_xi);
 
 /* Number of fluid voxels.  Valid after set_geometry. */
@@ -122,7 +126,8 @@ mclbm_status mclbm_boundary_count(const mclbm_lattice* lat, int64_t* count);
 
 /* Initial state f_i^(sigma) = w_i rho^(sigma) (fluid at rest).
  * d_rho: float[2][N] (component-major); values at solid voxels are ignored.
- * Resets the step counter to 0. */
+ * Resets the step counter to 0 and makes x periodic again (open planes
+ * capture their held populations from the state they are opened on). */
 mclbm_status mclbm_init_equilibrium(mclbm_lattice* lat, const float* d_rho);
 
 /* Advance nsteps >= 0 time steps (Eq. 1: collide with Eqs. 2, 6-11, 13-15,
@@ -151,7 +156,8 @@ mclbm_status mclbm_get_time(const mclbm_lattice* lat, int64_t* t);
  *   calls only change rho1_in / rho2_out (e.g. an inlet-density ramp between
  *   step calls).  Needs an initialised state and nx >= 6; densities must be
  *   finite and > 0.
- * enable = 0: periodic x again (the held values are dropped).
+ * enable = 0: periodic x again (the held values are dropped).  set_geometry,
+ *   init_equilibrium and load_state also return x to periodic.
  * Readouts still cover the whole lattice (values on the ghost planes carry
  * no physical meaning); the diagnostics' sums and maxima then leave the ghost
  * planes out.  The adjoint entry points refuse a lattice with open planes. */
@@ -190,7 +196,11 @@ mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]);
 /* Checkpoint / restore of the full state (populations, the density field
  * the FP16/BF16 codecs decode against, and the step counter).
  * d_dst / d_src: device buffers of mclbm_state_bytes bytes, 256-byte
- * aligned.  Restoring reproduces later steps bit for bit. */
+ * aligned.  Restoring reproduces later steps bit for bit.  Populations are
+ * stored per fluid voxel, so load_state refuses (EINVAL, nothing changed) a
+ * state saved for another shape, storage form or solid mask (the header
+ * keeps the fluid count and a fingerprint of the mask).  load_state makes x
+ * periodic again. */
 mclbm_status mclbm_state_bytes(const mclbm_lattice* lat, size_t* bytes);
 mclbm_status mclbm_save_state(mclbm_lattice* lat, void* d_dst);
 mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src);
@@ -229,8 +239,11 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
                                      size_t bytes);
 
 /* Reverse sweep: dL/dxi for the loss at the current time level, through the
- * nsteps steps recorded by mclbm_step_checkpointed (same nsteps and every;
- * the lattice must not have been stepped since).  Each segment of `every`
+ * nsteps steps recorded by the last mclbm_step_checkpointed on this lattice:
+ * d_ckpt, nsteps and every must be that call's (EINVAL otherwise), ckpt_bytes
+ * the size of d_ckpt (EINVAL below mclbm_checkpoint_bytes), and nothing may
+ * have changed the state since -- a step, init_equilibrium, load_state,
+ * set_geometry or set_open_x (ESTATE otherwise).  Each segment of `every`
  * steps is recomputed from its checkpoint into d_work, then the adjoint
  * steps run backwards through it (adjoint of streaming with bounce-back,
  * of the forced collision, Eqs. 1-2, 6-9, and of the forces and virtual
@@ -242,7 +255,8 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
  * lattice's stream by events; the gradient is complete when the lattice's
  * stream reaches the end of the call's work. */
 mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
-                                const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi);
+                                size_t ckpt_bytes, const uint8_t* d_region, void* d_work, size_t work_bytes,
+                                double* d_grad_xi);
 
 /* The same reverse sweep for the outlet flux of mclbm_loss_flux (same
  * arguments, work buffer and output).  The flux depends on the forces at
@@ -250,7 +264,8 @@ mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t ever
  * sums there: xi receives a direct term through the final virtual solid
  * densities (Eqs. 14-15) besides the one carried back through the steps. */
 mclbm_status mclbm_gradient_flux(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
-                                 const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi);
+                                 size_t ckpt_bytes, const uint8_t* d_region, void* d_work, size_t work_bytes,
+                                 double* d_grad_xi);
 
 /* Per-kernel timing of mclbm_step with HIP events recorded on the lattice's
  * stream around each launch (measurement support; two event records per

@@ -102,7 +102,7 @@ __device__ __forceinline__ int block_rank(bool flag, int* wave_off, int* count) 
 
 __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* __restrict__ xi,
                                  Geo g, const int* __restrict__ offsets, int* __restrict__ list,
-                                 float* __restrict__ xil, int* __restrict__ bad) {
+                                 float* __restrict__ xil) {
     __shared__ int wave_off[TN / 64];
     int x0, y0, z0;
     tile_origin(blockIdx.x, g, x0, y0, z0);
@@ -111,16 +111,50 @@ __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* 
     const bool flag = x < g.nx && y < g.ny && z < g.nz && is_boundary_solid(nbm[idx]);
     int cnt;
     const int rank = block_rank(flag, wave_off, &cnt);
-    bool invalid = false;
     if (flag) {
-        const float v = xi[idx];
         const int at = offsets[blockIdx.x] + rank;
         list[at] = idx;
-        xil[at] = v;
-        invalid = !(fabsf(v) < 1.0f);
+        xil[at] = xi[idx];
     }
-    const int any_bad = __syncthreads_or(invalid);
-    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) bad[blockIdx.x] = any_bad;
+}
+
+// 64-bit finaliser of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a
+// bijective mixing of a node index, summed over the solid nodes to
+// fingerprint a solid mask.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Validation of a candidate geometry before anything is committed:
+// out[0] += boundary solids whose |xi| is not < 1, out[1] += fluid nodes,
+// out[2] += sum of mix64(idx) over solid nodes (integer sums, so the result
+// does not depend on the order of the blocks).  One thread per node.
+__global__ __launch_bounds__(256) void k_geometry_check(const uint32_t* __restrict__ nbm,
+                                                        const float* __restrict__ xi, Geo g,
+                                                        unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[4];
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    bool bad = false, fluid = false;
+    unsigned long long h = 0;
+    if (idx < (uint32_t)g.n) {
+        const uint32_t m = nbm[idx];
+        fluid = !(m & SELF_SOLID);
+        if (is_boundary_solid(m)) bad = !(fabsf(xi[idx]) < 1.0f);
+        if (!fluid) h = mix64(idx);
+    }
+    const int nbad = __syncthreads_count(bad);
+    const int nfluid = __syncthreads_count(fluid);
+    for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = h;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (nbad) atomicAdd(out, (unsigned long long)nbad);
+        if (nfluid) atomicAdd(out + 1, (unsigned long long)nfluid);
+        atomicAdd(out + 2, part[0] + part[1] + part[2] + part[3]);
+    }
 }
 
 // Per tile: number of fluid nodes (into cnt and, for the scans, into base
@@ -570,12 +604,19 @@ void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hi
 int boundary_blocks(const Geo& g) { return tile_count(g); }
 
 void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int* total, int* list,
-                          float* xil, int* bad, const Geo& g, hipStream_t s) {
+                          float* xil, const Geo& g, hipStream_t s) {
     const int nb = boundary_blocks(g);
     hipLaunchKernelGGL(k_boundary_count, dim3(nb), dim3(TX, TY, TZ), 0, s, nbm, g, counts);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, nb, total);
     hipLaunchKernelGGL(k_boundary_write, dim3(nb), dim3(TX, TY, TZ), 0, s, nbm, xi, g,
-                       (const int*)counts, list, xil, bad);
+                       (const int*)counts, list, xil);
+}
+
+void launch_geometry_check(const uint32_t* nbm, const float* xi, const Geo& g, unsigned long long* out,
+                           hipStream_t s) {
+    const uint64_t zero[4] = {0, 0, 0, 0};
+    launch_store_words((uint64_t*)out, zero, s);
+    hipLaunchKernelGGL(k_geometry_check, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, nbm, xi, g, out);
 }
 
 void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, int* apos, int* totals,

@@ -19,7 +19,13 @@ void launch_store_words(uint64_t* dst, const uint64_t (&w)[4], hipStream_t s);
 void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hipStream_t s);
 int boundary_blocks(const Geo& g);
 void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int* total, int* list,
-                          float* xil, int* bad, const Geo& g, hipStream_t s);
+                          float* xil, const Geo& g, hipStream_t s);
+// Checks a candidate geometry (neighbour words nbm, adhesion xi) without
+// changing anything else: out[0] <- boundary solids with |xi| not < 1,
+// out[1] <- fluid nodes, out[2] <- order-independent fingerprint of the
+// solid mask.  Stream-ordered; out is cleared first.
+void launch_geometry_check(const uint32_t* nbm, const float* xi, const Geo& g, unsigned long long* out,
+                           hipStream_t s);
 int tile_count(const Geo& g);
 // Per-tile fluid counts and their scans: totals[0] <- number of fluid nodes,
 // totals[1] <- number of tiles holding fluid.

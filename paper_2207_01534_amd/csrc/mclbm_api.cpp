@@ -38,7 +38,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t elem_bytes(int storage) { return storage == MCLBM_F32 ? 4 : 2; }
 
 struct Layout {
-    size_t mv, rest, R0, R1, nbm, list, xil, counts, bad, partial, misc, total;
+    size_t mv, rest, R0, R1, nbm, list, xil, counts, partial, misc, total;
     size_t fid, loc, tcnt, tbase, tapos, tact, held;
     size_t mv_bytes, rest_bytes, r_bytes;
     int np, cap;
@@ -76,7 +76,6 @@ Layout make_layout(const mclbm_params& p) {
     L.list = take(n * sizeof(int));
     L.xil = take(n * sizeof(float));
     L.counts = take((size_t)boundary_blocks(g) * sizeof(int));
-    L.bad = take((size_t)boundary_blocks(g) * sizeof(int));
     L.partial = take((size_t)fields_blocks(g) * 8 * sizeof(double));
     L.fid = take(n * sizeof(int));
     L.loc = take((size_t)L.cap * sizeof(uint16_t));
@@ -123,6 +122,18 @@ struct mclbm_lattice {
     int nactive;
     bool geometry;
     bool initialized;
+    uint64_t geo_hash = 0;   // fingerprint of the solid mask (k_geometry_check)
+    // Bumped by every call that changes the geometry or the state, so that a
+    // reverse sweep can tell whether the state is still the one its
+    // checkpoints led to.
+    uint64_t generation = 0;
+    struct {
+        uint64_t generation;  // lattice generation right after the recording
+        const void* ckpt;
+        size_t bytes;
+        int32_t nsteps, every;
+        bool valid;
+    } record{};
     // open inlet/outlet planes along x (lbm_open.hip)
     bool open = false;
     float rho_in = 0.f, rho_out = 0.f;
@@ -143,6 +154,7 @@ struct mclbm_lattice {
     double* diag_out() const { return (double*)(ws + L.misc + 64); }     // 8 doubles
     double* open_out() const { return (double*)(ws + L.misc + 128); }    // 2 doubles
     int* open_count() const { return (int*)(ws + L.misc + 160); }
+    unsigned long long* check_out() const { return (unsigned long long*)(ws + L.misc + 192); }  // 3 words
     float* held() const { return (float*)(ws + L.held); }
     int* fid() const { return (int*)(ws + L.fid); }
     Sparse sparse() const {
@@ -234,37 +246,45 @@ mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t 
 mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, const float* d_xi) {
     if (!lat || !d_solid || !d_xi) return fail(MCLBM_EINVAL, "NULL argument");
     const Geo& g = lat->g;
-    launch_neighbour_bits(d_solid, lat->nbm(), g, lat->stream);
-    int* counts = (int*)(lat->ws + lat->L.counts);
-    int* bad = (int*)(lat->ws + lat->L.bad);
-    launch_boundary_list(lat->nbm(), d_xi, counts, lat->misc_int(), lat->list(), lat->xil(), bad, g,
-                         lat->stream);
     const Layout& L = lat->L;
+    hipStream_t s = lat->stream;
+    // Validate first, committing nothing: the candidate neighbour words go to
+    // the psi-hat field of the current level, which every step and readout
+    // rewrites before reading it, so a refused geometry leaves the lattice's
+    // geometry and state as they were.
+    uint32_t* cand = (uint32_t*)lat->R((int)(lat->t & 1));
+    launch_neighbour_bits(d_solid, cand, g, s);
+    launch_geometry_check(cand, d_xi, g, lat->check_out(), s);
+    HIP_TRY(hipGetLastError());
+    unsigned long long chk[3] = {0, 0, 0};  // bad xi, fluid nodes, mask fingerprint
+    HIP_TRY(hipMemcpyAsync(chk, lat->check_out(), sizeof(chk), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (chk[0]) return fail(MCLBM_EINVAL, "|xi| must be < 1 at solid voxels with a fluid neighbour");
+    if (chk[1] > (unsigned long long)L.cap) return fail(MCLBM_EINVAL, "more fluid voxels than params.fluid_capacity");
+    // commit
+    lat->geometry = false;
+    lat->initialized = false;
+    lat->open = false;
+    lat->record.valid = false;
+    lat->generation += 1;
+    HIP_TRY(hipMemcpyAsync(lat->nbm(), cand, (size_t)g.n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    int* counts = (int*)(lat->ws + L.counts);
+    launch_boundary_list(lat->nbm(), d_xi, counts, lat->misc_int(), lat->list(), lat->xil(), g, s);
     int* tcnt = (int*)(lat->ws + L.tcnt);
     int* tbase = (int*)(lat->ws + L.tbase);
     int* tapos = (int*)(lat->ws + L.tapos);
-    launch_tile_census(lat->nbm(), g, tcnt, tbase, tapos, lat->misc_int() + 1, lat->stream);
-    HIP_TRY(hipGetLastError());
-    const int nb = boundary_blocks(g);
-    std::vector<int> hbad(nb);
-    int totals[3] = {0, 0, 0};  // boundary solids, fluid nodes, active tiles
-    HIP_TRY(hipMemcpyAsync(totals, lat->misc_int(), sizeof(totals), hipMemcpyDeviceToHost, lat->stream));
-    HIP_TRY(hipMemcpyAsync(hbad.data(), bad, nb * sizeof(int), hipMemcpyDeviceToHost, lat->stream));
-    HIP_TRY(hipStreamSynchronize(lat->stream));
-    lat->geometry = false;
-    lat->initialized = false;
-    for (int b = 0; b < nb; ++b)
-        if (hbad[b]) return fail(MCLBM_EINVAL, "|xi| must be < 1 at solid voxels with a fluid neighbour");
-    if (totals[1] > L.cap) return fail(MCLBM_EINVAL, "more fluid voxels than params.fluid_capacity");
-    // fluid ids are assigned only once they are known to fit the capacity
+    launch_tile_census(lat->nbm(), g, tcnt, tbase, tapos, lat->misc_int() + 1, s);
     launch_tile_ids(lat->nbm(), g, tcnt, tbase, tapos, lat->fid(), (uint16_t*)(lat->ws + L.loc),
-                    (int*)(lat->ws + L.tact), lat->stream);
+                    (int*)(lat->ws + L.tact), s);
     HIP_TRY(hipGetLastError());
+    int totals[3] = {0, 0, 0};  // boundary solids, fluid nodes, active tiles
+    HIP_TRY(hipMemcpyAsync(totals, lat->misc_int(), sizeof(totals), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     lat->nbound = totals[0];
     lat->nfluid = totals[1];
     lat->nactive = totals[2];
+    lat->geo_hash = chk[2];
     lat->geometry = true;
-    lat->initialized = false;
     lat->t = 0;
     return MCLBM_OK;
 }
@@ -294,6 +314,9 @@ mclbm_status mclbm_init_equilibrium(mclbm_lattice* lat, const float* d_rho) {
     HIP_TRY(hipGetLastError());
     lat->t = 0;
     lat->initialized = true;
+    lat->open = false;  // held entering populations belong to the state they were captured from
+    lat->record.valid = false;
+    lat->generation += 1;
     return MCLBM_OK;
 }
 
@@ -333,6 +356,7 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
         });
         lat->t += 1;
     }
+    if (nsteps > 0) lat->generation += 1;
     HIP_TRY(hipGetLastError());
     HIP_TRY(mark_err);
     return MCLBM_OK;
@@ -341,6 +365,7 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
 mclbm_status mclbm_set_open_x(mclbm_lattice* lat, int32_t enable, double rho1_in, double rho2_out) {
     if (!lat) return fail(MCLBM_EINVAL, "NULL handle");
     if (!enable) {
+        if (lat->open) lat->generation += 1;
         lat->open = false;
         return MCLBM_OK;
     }
@@ -365,6 +390,7 @@ mclbm_status mclbm_set_open_x(mclbm_lattice* lat, int32_t enable, double rho1_in
     lat->rho_in = (float)rho1_in;
     lat->rho_out = (float)rho2_out;
     lat->open = true;
+    lat->generation += 1;
     return MCLBM_OK;
 }
 
@@ -428,12 +454,18 @@ mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]) {
 }
 
 // Saved state: [header 256 B][moving planes][rest planes][previous-level densities]
+// Populations are indexed by fluid id, so a state fits only a lattice with
+// the same solid mask: the header keeps the fluid count and the mask's
+// fingerprint.
 struct StateHeader {
     uint64_t magic;
     int64_t t;
     int32_t nx, ny, nz, storage;
+    int64_t nfluid;
+    uint64_t geo_hash;
+    uint64_t pad[2];
 };
-static constexpr uint64_t kMagic = 0x4d434c424d535431ull;  // "MCLBMST1"
+static constexpr uint64_t kMagic = 0x4d434c424d535432ull;  // "MCLBMST2"
 
 mclbm_status mclbm_state_bytes(const mclbm_lattice* lat, size_t* bytes) {
     if (!lat || !bytes) return fail(MCLBM_EINVAL, "NULL argument");
@@ -448,11 +480,12 @@ mclbm_status mclbm_save_state(mclbm_lattice* lat, void* d_dst) {
     if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
     const Layout& L = lat->L;
     char* dst = (char*)d_dst;
-    StateHeader h{kMagic, lat->t, lat->p.nx, lat->p.ny, lat->p.nz, lat->p.storage};
-    uint64_t words[4];
-    static_assert(sizeof(h) == sizeof(words), "header is four 64-bit words");
+    StateHeader h{kMagic, lat->t, lat->p.nx, lat->p.ny, lat->p.nz, lat->p.storage, lat->nfluid, lat->geo_hash, {0, 0}};
+    uint64_t words[8];
+    static_assert(sizeof(h) == sizeof(words), "header is eight 64-bit words");
     std::memcpy(words, &h, sizeof(h));
-    launch_store_words((uint64_t*)dst, words, lat->stream);
+    launch_store_words((uint64_t*)dst, {words[0], words[1], words[2], words[3]}, lat->stream);
+    launch_store_words((uint64_t*)dst + 4, {words[4], words[5], words[6], words[7]}, lat->stream);
     size_t off = kAlign;
     HIP_TRY(hipMemcpyAsync(dst + off, lat->ws + L.mv, L.mv_bytes, hipMemcpyDeviceToDevice, lat->stream));
     off += align_up(L.mv_bytes, kAlign);
@@ -475,6 +508,8 @@ mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src) {
     if (h.magic != kMagic || h.nx != lat->p.nx || h.ny != lat->p.ny || h.nz != lat->p.nz ||
         h.storage != lat->p.storage || h.t < 0)
         return fail(MCLBM_EINVAL, "state buffer does not match this lattice");
+    if (h.nfluid != lat->nfluid || h.geo_hash != lat->geo_hash)
+        return fail(MCLBM_EINVAL, "state buffer was saved under another solid mask");
     size_t off = kAlign;
     HIP_TRY(hipMemcpyAsync(lat->ws + L.mv, src + off, L.mv_bytes, hipMemcpyDeviceToDevice, lat->stream));
     off += align_up(L.mv_bytes, kAlign);
@@ -484,6 +519,9 @@ mclbm_status mclbm_load_state(mclbm_lattice* lat, const void* d_src) {
                            lat->stream));
     lat->t = h.t;
     lat->initialized = true;
+    lat->open = false;  // held entering populations belong to the state they were captured from
+    lat->record.valid = false;
+    lat->generation += 1;
     return MCLBM_OK;
 }
 
@@ -597,6 +635,12 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
         mclbm_status st = mclbm_step(lat, 1);
         if (st != MCLBM_OK) return st;
     }
+    lat->record.generation = lat->generation;
+    lat->record.ckpt = d_ckpt;
+    lat->record.bytes = bytes;
+    lat->record.nsteps = nsteps;
+    lat->record.every = every;
+    lat->record.valid = true;
     return MCLBM_OK;
 }
 
@@ -627,14 +671,22 @@ static hipError_t ensure_aux(mclbm_lattice* lat) {
 enum class LossKind { Snw, Flux };
 
 static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, int32_t every, const void* d_ckpt,
-                             const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
+                             size_t ckpt_bytes, const uint8_t* d_region, void* d_work, size_t work_bytes,
+                             double* d_grad_xi) {
     if (!lat || !d_ckpt || !d_region || !d_work || !d_grad_xi || nsteps < 1 || every < 1)
         return fail(MCLBM_EINVAL, "bad argument");
     if (lat->p.storage != MCLBM_F32) return fail(MCLBM_EINVAL, "loss and adjoint need FP32 storage");
     if (((uintptr_t)d_work) % kAlign || ((uintptr_t)d_ckpt) % kAlign)
         return fail(MCLBM_EINVAL, "work and checkpoint buffers must be 256-byte aligned");
     if (lat->open) return fail(MCLBM_EINVAL, "the adjoint covers periodic x only (open planes are enabled)");
-    if (!lat->initialized || lat->t < nsteps) return fail(MCLBM_ESTATE, "state is not nsteps past the checkpoints");
+    size_t need = 0;
+    mclbm_checkpoint_bytes(lat, nsteps, every, &need);
+    if (ckpt_bytes < need) return fail(MCLBM_EINVAL, "checkpoint buffer smaller than nsteps / every need");
+    if (!lat->initialized || !lat->record.valid || lat->record.generation != lat->generation)
+        return fail(MCLBM_ESTATE, "the state is not the one left by the last step_checkpointed "
+                                  "(the lattice was stepped, re-initialised or reloaded since)");
+    if (lat->record.ckpt != d_ckpt || lat->record.nsteps != nsteps || lat->record.every != every)
+        return fail(MCLBM_EINVAL, "checkpoints, nsteps or every differ from the last step_checkpointed");
     const AdjointWork W = adjoint_layout(lat, every, (char*)d_work);
     if (work_bytes < W.total) return fail(MCLBM_EINVAL, "work buffer too small");
     const Layout& L = lat->L;
@@ -745,13 +797,15 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
 }
 
 mclbm_status mclbm_gradient_snw(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
-                                const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
-    return gradient(lat, LossKind::Snw, nsteps, every, d_ckpt, d_region, d_work, work_bytes, d_grad_xi);
+                                size_t ckpt_bytes, const uint8_t* d_region, void* d_work, size_t work_bytes,
+                                double* d_grad_xi) {
+    return gradient(lat, LossKind::Snw, nsteps, every, d_ckpt, ckpt_bytes, d_region, d_work, work_bytes, d_grad_xi);
 }
 
 mclbm_status mclbm_gradient_flux(mclbm_lattice* lat, int32_t nsteps, int32_t every, const void* d_ckpt,
-                                 const uint8_t* d_region, void* d_work, size_t work_bytes, double* d_grad_xi) {
-    return gradient(lat, LossKind::Flux, nsteps, every, d_ckpt, d_region, d_work, work_bytes, d_grad_xi);
+                                 size_t ckpt_bytes, const uint8_t* d_region, void* d_work, size_t work_bytes,
+                                 double* d_grad_xi) {
+    return gradient(lat, LossKind::Flux, nsteps, every, d_ckpt, ckpt_bytes, d_region, d_work, work_bytes, d_grad_xi);
 }
 
 static void drop_events(mclbm_lattice* lat) {

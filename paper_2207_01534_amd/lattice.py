@@ -15,7 +15,7 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmclbm.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 _lib = None
 
@@ -70,8 +70,8 @@ SIGNATURES = [
     ("mclbm_checkpoint_bytes", _I32, [_VP, _I32, _I32, _SZP]),
     ("mclbm_adjoint_work_bytes", _I32, [_VP, _I32, _SZP]),
     ("mclbm_step_checkpointed", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t]),
-    ("mclbm_gradient_snw", _I32, [_VP, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
-    ("mclbm_gradient_flux", _I32, [_VP, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    ("mclbm_gradient_snw", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t, _VP, _VP, ctypes.c_size_t, _VP]),
+    ("mclbm_gradient_flux", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t, _VP, _VP, ctypes.c_size_t, _VP]),
     ("mclbm_set_open_x", _I32, [_VP, _I32, ctypes.c_double, ctypes.c_double]),
     ("mclbm_open_x_pressure", _I32, [_VP, ctypes.POINTER(ctypes.c_double)]),
     ("mclbm_profile", _I32, [_VP, _I32]),
@@ -279,8 +279,8 @@ class Lattice:
         _check(_lib.mclbm_adjoint_work_bytes(self._h, int(every), ctypes.byref(b)), "adjoint_work_bytes")
         work = torch.empty(b.value, dtype=torch.uint8, device=self.device)
         grad = torch.empty(self.dims, dtype=torch.float64, device=self.device)
-        _check(fn(self._h, int(nsteps), int(every), _ptr(checkpoints), _ptr(reg), _ptr(work), b.value, _ptr(grad)),
-               what)
+        _check(fn(self._h, int(nsteps), int(every), _ptr(checkpoints), checkpoints.numel() * checkpoints.element_size(),
+                  _ptr(reg), _ptr(work), b.value, _ptr(grad)), what)
         self._keep = (reg, work)
         return grad
 

@@ -259,3 +259,45 @@ def test_flux_gradient_against_oracle_fd(steps, every):
     dd, dd_half = directional(eps), directional(eps / 2)
     assert dd_half == pytest.approx(dd, rel=1e-5, abs=1e-6 * scale)
     assert float((grad * v).sum()) == pytest.approx(dd_half, rel=1e-3, abs=1e-3 * scale)
+
+
+def test_reverse_sweep_refuses_a_state_it_was_not_recorded_for():
+    """The reverse sweep differentiates the run recorded by the last
+    step_checkpointed: a step, a re-initialisation or a second recording in
+    between, other nsteps / every, another checkpoint buffer or one smaller
+    than nsteps / every need are refused, and an untouched record still gives
+    the same gradient bit for bit (twice in a row)."""
+    import torch
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams, MclbmError
+    shape = (12, 10, 8)
+    solid = wl.random_mask(shape, 0.25, seed=91)
+    xi = wl.uniform_xi(solid, -0.4, 0.4, seed=92)
+    rho = wl.tanh_droplet(shape, 3.0)
+    rho[:, solid != 0] = 0
+    rho_t = torch.as_tensor(rho.astype(np.float32), device="cuda")
+    lat = Lattice(LatticeParams(shape=shape, tau=(1.5, 0.6)), torch.as_tensor(solid), torch.as_tensor(xi), rho_t)
+    reg = torch.ones(shape[::-1], dtype=torch.uint8, device="cuda")
+    ck = lat.step_checkpointed(6, 2)
+    g1 = lat.gradient_snw(6, 2, ck, reg)
+    g2 = lat.gradient_snw(6, 2, ck, reg)
+    assert torch.equal(g1, g2)
+    for bad in ((5, 2), (6, 3)):
+        with pytest.raises(MclbmError):
+            lat.gradient_snw(*bad, ck, reg)
+    with pytest.raises(MclbmError):
+        lat.gradient_snw(6, 2, ck[: ck.numel() // 2], reg)     # smaller than 3 checkpoints
+    other = torch.empty_like(ck)
+    other.copy_(ck)
+    with pytest.raises(MclbmError):
+        lat.gradient_snw(6, 2, other, reg)                     # not the buffer that was recorded
+    lat.step(1)
+    with pytest.raises(MclbmError):
+        lat.gradient_snw(6, 2, ck, reg)                        # stepped since the recording
+    lat.init_equilibrium(rho_t)
+    ck_a = lat.step_checkpointed(6, 2)
+    lat.init_equilibrium(rho_t)
+    ck_b = lat.step_checkpointed(6, 2)
+    with pytest.raises(MclbmError):
+        lat.gradient_snw(6, 2, ck_a, reg)                      # superseded by the second recording
+    g3 = lat.gradient_snw(6, 2, ck_b, reg)
+    assert torch.equal(g1, g3)

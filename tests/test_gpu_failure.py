@@ -53,3 +53,30 @@ def test_blow_up_is_detected_and_a_saved_state_restores():
     assert d["mass1"] == good["mass1"] and d["mass2"] == good["mass2"]
     torch.cuda.synchronize()
     assert torch.equal(lat.density(), rho_saved)
+
+
+def test_state_of_another_solid_mask_is_refused():
+    """Populations are stored per fluid voxel: a state saved under one solid
+    mask does not fit another mask of the same shape (nor of the same fluid
+    count) and is refused, leaving the lattice's own state untouched."""
+    import torch
+    from paper_2207_01534_amd.lattice import MclbmError
+    shape = (16, 12, 10)
+    solid_a = wl.random_mask(shape, 0.25, seed=41)
+    solid_b = np.roll(solid_a, 1, axis=2)               # same fluid count, other voxels
+    solid_c = wl.random_mask(shape, 0.3, seed=42)
+    xi = np.zeros(solid_a.shape, np.float32)
+    rho = wl.tanh_droplet(shape, 3.0)
+    lat_a = gpu_case(shape, solid_a, xi, np.where(solid_a[None] != 0, 0, rho), TAU, 3.5, ((0, 0, 0), (0, 0, 0)))
+    lat_a.step(3)
+    saved_a = lat_a.save()
+    for solid in (solid_b, solid_c):
+        lat = gpu_case(shape, solid, xi, np.where(solid[None] != 0, 0, rho), TAU, 3.5, ((0, 0, 0), (0, 0, 0)))
+        lat.step(2)
+        before = lat.density()
+        with pytest.raises(MclbmError):
+            lat.load(saved_a)
+        assert lat.time == 2 and torch.equal(lat.density(), before)
+    lat_a.step(2)
+    lat_a.load(saved_a)                                  # its own mask: accepted
+    assert lat_a.time == 3

@@ -164,3 +164,39 @@ def test_open_planes_refuse_solid_on_required_planes():
     with pytest.raises(MclbmError):
         lat.set_open_x(RHO_IN, RHO_OUT)
     lat.step(2)                                               # still periodic and usable
+
+
+def test_new_geometry_state_or_load_returns_x_to_periodic():
+    """Open planes hold populations captured from one state: set_geometry,
+    init_equilibrium and load_state return x to periodic, so the adjoint (which
+    refuses open planes) accepts the lattice again, and reopening checks the
+    planes of the new geometry before anything is captured."""
+    import torch
+    from paper_2207_01534_amd.lattice import MclbmError
+    gshape, gsolid, gxi, grho, _, _, _, _ = _case()
+    lat = gpu_case(gshape, gsolid, gxi, grho, TAU, G, ((0, 0, 0), (0, 0, 0)))
+    saved = lat.save()
+    rho32 = torch.as_tensor(np.asarray(grho, np.float32))
+    for reset in ("geometry", "init", "load"):
+        print(f"[case] open planes then {reset}", flush=True)
+        lat.set_open_x(RHO_IN, RHO_OUT)
+        with pytest.raises(MclbmError):
+            lat.step_checkpointed(2, 1)
+        if reset == "geometry":
+            lat.set_geometry(torch.as_tensor(gsolid), torch.as_tensor(np.asarray(gxi, np.float32)))
+            lat.init_equilibrium(rho32)
+        elif reset == "init":
+            lat.init_equilibrium(rho32)
+        else:
+            lat.load(saved)
+        lat.step_checkpointed(2, 1)                           # periodic again
+        assert lat.diagnostics()["nonfinite"] == 0
+    blocked = gsolid.copy()
+    blocked[3, 4, 1] = 1                                      # the inlet plane x = 1 must be fluid
+    lat.set_open_x(RHO_IN, RHO_OUT)
+    lat.set_geometry(torch.as_tensor(blocked), torch.as_tensor(np.asarray(gxi, np.float32)))
+    lat.init_equilibrium(rho32)
+    with pytest.raises(MclbmError):
+        lat.set_open_x(RHO_IN, RHO_OUT)                      # checked again on the new geometry
+    lat.step(2)
+    assert lat.diagnostics()["nonfinite"] == 0

@@ -129,10 +129,11 @@ def test_fluid_capacity_enforced_and_used():
 
 def test_xi_out_of_range_refused_only_where_it_is_read():
     """chi = 1 +- xi (Eqs. 14-15 and the rule after them) must stay positive:
-    |xi| >= 1 at a solid voxel with a fluid neighbour is refused and leaves
-    the lattice without geometry; at a solid voxel deep inside a grain xi is
-    never read and any value is accepted; a valid geometry afterwards restores
-    a working lattice."""
+    |xi| >= 1 at a solid voxel with a fluid neighbour is refused before
+    anything is replaced -- the lattice keeps its geometry, state and step
+    counter and steps on exactly as a twin that never saw the refused call;
+    at a solid voxel deep inside a grain xi is never read and any value is
+    accepted."""
     import torch
     from paper_2207_01534_amd.lattice import MclbmError
     shape = (24, 16, 12)
@@ -143,16 +144,47 @@ def test_xi_out_of_range_refused_only_where_it_is_read():
     rho[:, solid != 0] = 0
     xi = np.where(solid != 0, 0.2, 0.0).astype(np.float32)
     lat = gpu_case(shape, solid, xi, rho, (1.0, 1.0), 3.5, ((0, 0, 0), (0, 0, 0)))
+    twin = gpu_case(shape, solid, xi, rho, (1.0, 1.0), 3.5, ((0, 0, 0), (0, 0, 0)))
     deep = xi.copy()
     deep[5, 7, 10] = 1.5                               # inside the block
     lat.set_geometry(torch.as_tensor(solid), torch.as_tensor(deep))
+    lat.init_equilibrium(torch.as_tensor(rho.astype(np.float32)))
+    lat.step(3)
+    twin.step(3)
     face = xi.copy()
     face[3, 7, 10] = 1.0                               # on the block's face (fluid at z = 2)
     with pytest.raises(MclbmError):
         lat.set_geometry(torch.as_tensor(solid), torch.as_tensor(face))
-    with pytest.raises(MclbmError):
-        lat.fluid_count()                              # no geometry after the refusal
+    assert lat.time == 3 and lat.fluid_count() == int((solid == 0).sum())
+    lat.step(5)
+    twin.step(5)
+    assert torch.equal(lat.density(), twin.density())  # same geometry, same state, bit for bit
+    assert torch.equal(lat.velocity(), twin.velocity())
     lat.set_geometry(torch.as_tensor(solid), torch.as_tensor(xi))
     lat.init_equilibrium(torch.as_tensor(rho.astype(np.float32)))
     lat.step(4)
     assert lat.time == 4 and lat.diagnostics()["nonfinite"] == 0
+
+
+def test_geometry_beyond_capacity_refused_and_lattice_kept():
+    """A mask with more fluid voxels than the workspace holds is refused with
+    the lattice's geometry and state left as they were."""
+    import torch
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams, MclbmError
+    shape = (20, 12, 10)
+    nx, ny, nz = shape
+    solid = wl.random_mask(shape, 0.3, seed=31)
+    xi = wl.uniform_xi(solid, -0.3, 0.3, seed=32)
+    rho = wl.tanh_droplet(shape, 4.0)
+    rho[:, solid != 0] = 0
+    nf = int((solid == 0).sum())
+    lat = Lattice(LatticeParams(shape=shape, fluid_capacity=nf), torch.as_tensor(solid), torch.as_tensor(xi),
+                  torch.as_tensor(rho.astype(np.float32)))
+    lat.step(2)
+    before = lat.density()
+    with pytest.raises(MclbmError):
+        lat.set_geometry(torch.zeros((nz, ny, nx), dtype=torch.uint8), None)
+    assert lat.time == 2 and lat.fluid_count() == nf
+    assert torch.equal(lat.density(), before)
+    lat.step(1)
+    assert lat.time == 3 and lat.diagnostics()["nonfinite"] == 0
