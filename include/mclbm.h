@@ -193,6 +193,21 @@ mclbm_status mclbm_read_pressure(mclbm_lattice* lat, float* d_P);
  * Returns MCLBM_ENONFINITE (after filling h_out) if h_out[5] > 0. */
 mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]);
 
+/* mclbm_diagnostics for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, tight serving loops): the same outputs and
+ * errors, with the FP64 partials and results of the reduction kept in a
+ * device array of the library itself instead of the lattice's workspace --
+ * 4096 blocks of 8 partials plus 8 result words (256 KiB per GPU, held until
+ * the process ends).  Any lattice size fits: beyond 4096 patches of 64 x 4
+ * nodes each block sums several patches (the sums then group differently
+ * from mclbm_diagnostics, up to FP64 rounding; counts and the maximum are
+ * identical).  Allocates nothing.  The device that was current at
+ * mclbm_create must be current (EINVAL otherwise); the first call on a
+ * device looks the array up.  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (several threads or streams at once) race;
+ * calls in sequence do not. */
+mclbm_status mclbm_diagnostics_noalloc(mclbm_lattice* lat, double h_out[7]);
+
 /* Checkpoint / restore of the full state (populations, the density field
  * the FP16/BF16 codecs decode against, and the step counter).
  * d_dst / d_src: device buffers of mclbm_state_bytes bytes, 256-byte

@@ -17,6 +17,8 @@
 // Readouts and diagnostics reuse k_density + k_ivsd and then k_fields.
 #include "lbm_kernels.hpp"
 
+#include <mutex>
+
 namespace mclbm {
 
 // ---------------------------------------------------------------------------
@@ -474,7 +476,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
 
 // ---------------------------------------------------------------------------
 // Readouts and diagnostics at the current time level (psi already filled by
-// k_density + k_ivsd for this level).  Dense over all nodes.
+// k_density + k_ivsd for this level).  Dense over all nodes, in patches of
+// 64 x 4 nodes of one z plane numbered x fastest; block b handles patches
+// b, b + gridDim.x, ... (one patch each when the grid covers them all), so
+// the per-block FP64 partials hold a fixed set of patches summed in a fixed
+// order.
 // ---------------------------------------------------------------------------
 template <class C, bool ODD>
 __global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict__ fid,
@@ -484,12 +490,15 @@ __global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict
                                                     float* __restrict__ o_rho, float* __restrict__ o_u,
                                                     float* __restrict__ o_F, float* __restrict__ o_P,
                                                     double* __restrict__ partial, int skip_ghost_x) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    const bool inside = x < g.nx && y < g.ny;
+    const int gx = (g.nx + 63) / 64, gy = (g.ny + 3) / 4;
+    const int npatch = gx * gy * g.nz;
     double d[7] = {0, 0, 0, 0, 0, 0, 0};  // m1, m2, water, snw, |u|max, bad, nfluid
-    if (inside) {
+    for (int b = blockIdx.x; b < npatch; b += gridDim.x) {
+        const int bx = b % gx, r = b / gx;
+        const int x = bx * 64 + threadIdx.x;
+        const int y = (r % gy) * 4 + threadIdx.y;
+        const int z = r / gy;
+        if (!(x < g.nx && y < g.ny)) continue;
         const Nb nb(x, y, z, g);
         const uint32_t self = nb.idx;
         const size_t n = (size_t)g.n;
@@ -512,13 +521,13 @@ __global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict
             const double um = sqrt((double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
             // with open x planes the ghost planes stay out of the diagnostics
             if (!(skip_ghost_x && (x == 0 || x == g.nx - 1))) {
-                d[0] = r0;
-                d[1] = r1;
-                d[2] = r1 > r0 ? 1.0 : 0.0;
-                d[3] = r0 / (r0 + r1);
-                d[4] = um;
-                d[5] = (isfinite(rho[0]) && isfinite(rho[1]) && isfinite(um)) ? 0.0 : 1.0;
-                d[6] = 1.0;
+                d[0] += r0;
+                d[1] += r1;
+                d[2] += r1 > r0 ? 1.0 : 0.0;
+                d[3] += r0 / (r0 + r1);
+                d[4] = fmax(d[4], um);
+                d[5] += (isfinite(rho[0]) && isfinite(rho[1]) && isfinite(um)) ? 0.0 : 1.0;
+                d[6] += 1.0;
             }
         }
         if (o_rho) { o_rho[self] = rho[0]; o_rho[n + self] = rho[1]; }
@@ -547,8 +556,7 @@ __global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict
     if (tid < 7) {
         double v = red[0][tid];
         for (int w = 1; w < 4; ++w) v = (tid == 4) ? fmax(v, red[w][tid]) : v + red[w][tid];
-        const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        partial[(size_t)b * 8 + tid] = v;
+        partial[(size_t)blockIdx.x * 8 + tid] = v;
     }
 }
 
@@ -696,16 +704,41 @@ int fields_blocks(const Geo& g) {
 template <class C>
 void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, const float2* psi,
                    const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F, float* o_P,
-                   double* partial, double* out, int skip_ghost_x, hipStream_t s) {
+                   double* partial, double* out, int skip_ghost_x, hipStream_t s, int max_blocks) {
+    const int all = fields_blocks(g);
+    const int nb = max_blocks > 0 && max_blocks < all ? max_blocks : all;
     if (odd)
-        hipLaunchKernelGGL((k_fields<C, true>), tile_grid3(g), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
+        hipLaunchKernelGGL((k_fields<C, true>), dim3(nb), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
                            ph, o_rho, o_u, o_F, o_P, partial, skip_ghost_x);
     else
-        hipLaunchKernelGGL((k_fields<C, false>), tile_grid3(g), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
+        hipLaunchKernelGGL((k_fields<C, false>), dim3(nb), dim3(64, 4), 0, s, P, fid, nbm, rprev, psi, g,
                            ph, o_rho, o_u, o_F, o_P, partial, skip_ghost_x);
     if (partial)
-        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, (const double*)partial,
-                           fields_blocks(g), out);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, (const double*)partial, nb, out);
+}
+
+// The library's own device scratch for callers that cannot allocate (FP64
+// partials and results of the diagnostics reduction): one copy per GPU,
+// kept until the process ends.  Host code never passes the array's name to
+// a kernel; it uses the address hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = (double*)g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 #define MCLBM_INSTANTIATE(C)                                                                              \
@@ -718,7 +751,7 @@ void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const 
                                            hipStream_t);                                                  \
     template void launch_fields<C>(const Pops<C>&, const int*, const uint32_t*, const float2*,            \
                                    const float2*, const Geo&, const Phys&, int, float*, float*, float*,   \
-                                   float*, double*, double*, int, hipStream_t);
+                                   float*, double*, double*, int, hipStream_t, int);
 
 MCLBM_INSTANTIATE(CodecF32)
 MCLBM_INSTANTIATE(CodecF16)

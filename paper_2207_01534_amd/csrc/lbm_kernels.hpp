@@ -49,9 +49,21 @@ void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, 
                            const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, int odd,
                            hipStream_t s);
 int fields_blocks(const Geo& g);
+// Readouts and the diagnostics reduction.  max_blocks > 0 caps the grid (each
+// block then sums several 64 x 4 patches), which bounds the partials to
+// 8 * max_blocks doubles; 0 = one block per patch (fields_blocks).
 template <class C>
 void launch_fields(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, const float2* psi,
                    const Geo& g, const Phys& ph, int odd, float* o_rho, float* o_u, float* o_F, float* o_P,
-                   double* partial, double* out, int skip_ghost_x, hipStream_t s);
+                   double* partial, double* out, int skip_ghost_x, hipStream_t s, int max_blocks = 0);
+
+// Device scratch of the library itself (lbm_kernels.hip), for entry points
+// that allocate nothing: kScratchBlocks blocks of 8 partials, then 8 result
+// words.  scratch_address returns its address on `device`, which must be the
+// current device; the first call per device looks the symbol up.
+constexpr int kScratchBlocks = 4096;
+constexpr int kScratchDoubles = 8 * kScratchBlocks + 8;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int device, double** out);
 
 }  // namespace mclbm

@@ -115,6 +115,7 @@ struct mclbm_lattice {
     Phys ph;
     Layout L;
     hipStream_t stream;
+    int device = -1;  // current device at mclbm_create
     char* ws;
     int64_t t;
     int nbound;
@@ -187,7 +188,8 @@ struct mclbm_lattice {
         launch_ivsd(list(), xil(), nbound, nbm(), psi, g, stream);
         if (open) launch_open_mirror(psi, g, stream);
     }
-    void fields(float* o_rho, float* o_u, float* o_F, float* o_P, double* partial, double* out) {
+    void fields(float* o_rho, float* o_u, float* o_F, float* o_P, double* partial, double* out,
+                int max_blocks = 0) {
         fill_psi();
         const int odd = (int)(t & 1);
         const float2* psi = R((int)(t & 1));
@@ -195,7 +197,7 @@ struct mclbm_lattice {
         with_codec([&](auto c) {
             using C = decltype(c);
             launch_fields<C>(pops<C>(), fid(), nbm(), rprev, psi, g, ph, odd, o_rho, o_u, o_F, o_P, partial,
-                             out, open ? 1 : 0, stream);
+                             out, open ? 1 : 0, stream, max_blocks);
         });
     }
 };
@@ -232,6 +234,13 @@ mclbm_status mclbm_create(const mclbm_params* params, void* d_workspace, size_t 
     }
     lat->ph.G = (float)params->G;
     lat->stream = (hipStream_t)stream;
+    // creation itself does no device work (and succeeds without a device);
+    // the device only matters to the entry points that use the library's
+    // own per-device scratch
+    if (hipGetDevice(&lat->device) != hipSuccess) {
+        lat->device = -1;
+        (void)hipGetLastError();
+    }
     lat->ws = (char*)d_workspace;
     lat->t = 0;
     lat->nbound = 0;
@@ -436,13 +445,10 @@ mclbm_status mclbm_read_pressure(mclbm_lattice* lat, float* d_P) {
     return readout(lat, nullptr, nullptr, nullptr, d_P);
 }
 
-mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]) {
-    if (!lat || !h_out) return fail(MCLBM_EINVAL, "NULL argument");
-    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
-    lat->fields(nullptr, nullptr, nullptr, nullptr, lat->partial(), lat->diag_out());
+// Copies the reduced diagnostics to the host and turns counts into fractions.
+static mclbm_status finish_diagnostics(mclbm_lattice* lat, const double* d_out, double h_out[7]) {
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(h_out, lat->diag_out(), 7 * sizeof(double), hipMemcpyDeviceToHost,
-                           lat->stream));
+    HIP_TRY(hipMemcpyAsync(h_out, d_out, 7 * sizeof(double), hipMemcpyDeviceToHost, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     // the kernels return counts and sums; saturations are fractions of the fluid voxels
     if (h_out[6] > 0) {
@@ -451,6 +457,29 @@ mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]) {
     }
     if (h_out[5] > 0) return fail(MCLBM_ENONFINITE, "non-finite density or velocity");
     return MCLBM_OK;
+}
+
+mclbm_status mclbm_diagnostics(mclbm_lattice* lat, double h_out[7]) {
+    if (!lat || !h_out) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    lat->fields(nullptr, nullptr, nullptr, nullptr, lat->partial(), lat->diag_out());
+    return finish_diagnostics(lat, lat->diag_out(), h_out);
+}
+
+mclbm_status mclbm_diagnostics_noalloc(mclbm_lattice* lat, double h_out[7]) {
+    if (!lat || !h_out) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!lat->initialized) return fail(MCLBM_ESTATE, "state not initialised");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (lat->device < 0 || dev != lat->device)
+        return fail(MCLBM_EINVAL, "the device current at mclbm_create must be the current device");
+    double* scr = nullptr;
+    HIP_TRY(scratch_address(dev, &scr));
+    // at most kScratchBlocks partials whatever the lattice size: a larger
+    // lattice gives each block several patches to sum
+    double* out = scr + 8 * (size_t)kScratchBlocks;
+    lat->fields(nullptr, nullptr, nullptr, nullptr, scr, out, kScratchBlocks);
+    return finish_diagnostics(lat, out, h_out);
 }
 
 // Saved state: [header 256 B][moving planes][rest planes][previous-level densities]

@@ -62,6 +62,7 @@ SIGNATURES = [
     ("mclbm_read_force", _I32, [_VP, _VP]),
     ("mclbm_read_pressure", _I32, [_VP, _VP]),
     ("mclbm_diagnostics", _I32, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    ("mclbm_diagnostics_noalloc", _I32, [_VP, ctypes.POINTER(ctypes.c_double)]),
     ("mclbm_state_bytes", _I32, [_VP, _SZP]),
     ("mclbm_save_state", _I32, [_VP, _VP]),
     ("mclbm_load_state", _I32, [_VP, _VP]),
@@ -227,9 +228,13 @@ class Lattice:
         _check(_lib.mclbm_read_pressure(self._h, _ptr(o)), "read_pressure")
         return o
 
-    def diagnostics(self, raise_nonfinite=True) -> dict:
+    def diagnostics(self, raise_nonfinite=True, noalloc=False) -> dict:
+        """FP64 masses, saturations, max |u|, non-finite count and fluid count;
+        noalloc=True takes the entry point whose reduction scratch is the
+        library's own device array (no workspace memory)."""
         out = (ctypes.c_double * 7)()
-        st = _lib.mclbm_diagnostics(self._h, out)
+        fn = _lib.mclbm_diagnostics_noalloc if noalloc else _lib.mclbm_diagnostics
+        st = fn(self._h, out)
         if st == -3 and not raise_nonfinite:
             st = 0
         _check(st, "diagnostics")
