@@ -50,18 +50,31 @@ LOSS_MUTANTS = [
     ("loss_ignores_region", "if (solid[n] || !region[n]) continue;", "if (solid[n]) continue;"),
 ]
 
+# planted mistakes in the diagnostics (masses, S_w, largest speed, non-finite count)
+DIAG_MUTANTS = [
+    ("diag_water_is_component_1", "if (r2 > r1) nw += 1.0;", "if (r1 > r2) nw += 1.0;"),
+    ("diag_ties_count_as_water", "if (r2 > r1) nw += 1.0;", "if (r2 >= r1) nw += 1.0;"),
+    ("diag_counts_solid", "        if (solid[n]) continue;\n        double r1 = rho[n], r2 = rho[N + n];\n        m1 += r1;",
+     "        double r1 = rho[n], r2 = rho[N + n];\n        m1 += r1;"),
+    ("diag_speed_misses_z", " + u[2 * N + n] * u[2 * N + n]);", ");"),
+    ("diag_nonfinite_skips_rest", "            for (int i = 0; i < Q; ++i)\n                if (!isfinite",
+     "            for (int i = 1; i < Q; ++i)\n                if (!isfinite"),
+]
+
 PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
              os.path.join(ROOT, "tests", "test_oracle_physics.py") + "::test_single_fluid_poiseuille"]
 
 
 OPEN_PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_open.py")]
 LOSS_PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_loss.py")]
+DIAG_PIN_TESTS = [os.path.join(ROOT, "tests", "test_oracle_diagnostics.py")]
 
 
 @pytest.mark.parametrize("name,orig,planted,pins",
                          [m + (PIN_TESTS,) for m in MUTANTS] + [m + (OPEN_PIN_TESTS,) for m in OPEN_MUTANTS]
-                         + [m + (LOSS_PIN_TESTS,) for m in LOSS_MUTANTS],
-                         ids=[m[0] for m in MUTANTS + OPEN_MUTANTS + LOSS_MUTANTS])
+                         + [m + (LOSS_PIN_TESTS,) for m in LOSS_MUTANTS]
+                         + [m + (DIAG_PIN_TESTS,) for m in DIAG_MUTANTS],
+                         ids=[m[0] for m in MUTANTS + OPEN_MUTANTS + LOSS_MUTANTS + DIAG_MUTANTS])
 def test_planted_mistake_is_caught(name, orig, planted, pins, tmp_path):
     src = open(SRC).read()
     assert src.count(orig) == 1, name
