@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_loss_partial(Pops<CF> P, const int* __r
         if (!(m & SELF_SOLID) && region[nb.idx]) {
             float f[2][Q];
             load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx],
-                               [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
+                               [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np, 0.0f);
             const double r0 = sum19(f[0]), r1 = sum19(f[1]);
             v = r0 / (r0 + r1);
             c = 1.0;
@@ -110,7 +110,7 @@ __device__ __forceinline__ FluxNode flux_node(const Pops<CF>& P, const int* fid,
     FluxNode q;
     float f[2][Q];
     load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)fid[nb.idx], [&](int i, int s) { return fid[nb.at(i, s)]; },
-                       g.np);
+                       g.np, 0.0f);
     q.rho[0] = sum19(f[0]);
     q.rho[1] = sum19(f[1]);
     psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, q.A);
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const int* __restr
     if (region[nb.idx] && loss[1] > 0) {
         float f[2][Q];
         load_node<CF, ODD>(f, P, nullptr, m, nb, kf,
-                           [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
+                           [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np, 0.0f);
         const double r0 = sum19(f[0]), r1 = sum19(f[1]);
         const double rt = r0 + r1;
         const double s = 1.0 / (rt * rt * loss[1]);
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
     const uint32_t m = nbm[nb.idx];
     // forward quantities of this node at time t
     float f[2][Q];
-    load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)kf, [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
+    load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)kf, [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np, 0.0f);
     const float rho[2] = {sum19(f[0]), sum19(f[1])};
     float A[2][3];
     psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, A);

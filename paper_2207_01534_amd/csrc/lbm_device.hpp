@@ -103,43 +103,120 @@ struct Nb {
 // Storage codecs.  Moving populations (i = 1..18) are stored in type T; the
 // rest population of each component always stays FP32.
 //   F32:  stored value = f.
-//   F16 / BF16: stored value q = (f - w_i rho_w) / rhot_w, the offset of the
-//         population from its lattice-weight share of the writer's component
-//         density, scaled by the writer's total density rhot_w = rho1 + rho2
-//         (both at the previous time level, read back by the decoder from the
-//         same FP32 field).  Scaling by the total density keeps q bounded
-//         where one component's density vanishes; the decoder evaluates
-//         f = q rhot_w + w_i rho_w with one explicit FMA so that encoder and
-//         decoder agree bit for bit.
+//   F16 / BF16: stored value q = (f - p) / rhot_w, the deviation of the
+//         population from a predictor p of it, scaled by the total density
+//         rhot_w = rho1 + rho2 of the node that wrote it.  The predictor and
+//         the scale come from the writer's state at the previous time level
+//         as both the writing and the reading kernels see it (the
+//         pseudopotential field of that level, below), so they are the same
+//         numbers on both sides; the decoder evaluates f = q rhot_w + p with
+//         one explicit FMA and the encoder's mass balance uses the same
+//         expression, so encoder and decoder agree bit for bit.  Scaling by
+//         the total density keeps q bounded where one component's density
+//         vanishes.
 // ---------------------------------------------------------------------------
 struct CodecF32 {
     using T = float;
     static constexpr bool kRef = false;
-    __device__ static __forceinline__ float dec(T h, float, float, float) { return h; }
-    __device__ static __forceinline__ T enc(float f, float, float, float) { return f; }
+    __device__ static __forceinline__ float dec(T h, float, float) { return h; }
+    __device__ static __forceinline__ T enc(float f, float, float) { return f; }
 };
 
 struct CodecF16 {
     using T = __half;
     static constexpr bool kRef = true;
-    __device__ static __forceinline__ float dec(T h, float w, float rho_w, float rhot_w) {
-        return fmaf(__half2float(h), rhot_w, w * rho_w);
+    __device__ static __forceinline__ float dec(T h, float pred, float rhot_w) {
+        return fmaf(__half2float(h), rhot_w, pred);
     }
-    __device__ static __forceinline__ T enc(float f, float w, float rho_w, float inv_rhot_w) {
-        return __float2half_rn((f - w * rho_w) * inv_rhot_w);
+    __device__ static __forceinline__ T enc(float f, float pred, float inv_rhot_w) {
+        return __float2half_rn((f - pred) * inv_rhot_w);
     }
 };
 
 struct CodecBF16 {
     using T = __hip_bfloat16;
     static constexpr bool kRef = true;
-    __device__ static __forceinline__ float dec(T h, float w, float rho_w, float rhot_w) {
-        return fmaf(__bfloat162float(h), rhot_w, w * rho_w);
+    __device__ static __forceinline__ float dec(T h, float pred, float rhot_w) {
+        return fmaf(__bfloat162float(h), rhot_w, pred);
     }
-    __device__ static __forceinline__ T enc(float f, float w, float rho_w, float inv_rhot_w) {
-        return __float2bfloat16((f - w * rho_w) * inv_rhot_w);
+    __device__ static __forceinline__ T enc(float f, float pred, float inv_rhot_w) {
+        return __float2bfloat16((f - pred) * inv_rhot_w);
     }
 };
+
+// ---------------------------------------------------------------------------
+// Codec predictors (F16/BF16).  The post-collision population f*_j^(s) of a
+// node departs from its lattice-weight share w_j rho^(s) mostly through its
+// first moment, and at interfaces and walls that moment is dominated by the
+// component's own force: the cohesion and adhesion of Eqs. (11) and (13)
+// push component s down the gradient of the other component's
+// pseudopotential psi^(s'), and the Guo source of Eq. (9) with the half-force
+// shift puts about 3/2 w_j e_j.F^(s) into direction j.  Storing the deviation
+// from a predictor that follows this gradient leaves a much smaller number to
+// round.  Only the previous level's pseudopotential field psi-hat (rho at
+// fluid nodes, the virtual density of Eq. 15 at solid ones) is common to the
+// writer and all its readers, so the predictor uses nothing else:
+//   p^(s) = w_j rho^(s)(x) (1 - (G/4) D_j^(s')),
+// x the writing node, j the direction it writes, and D_j the difference of
+// psi^(s') along e_j:
+//   D_j = psi(x + e_j) - psi(x)        when x + e_j is fluid (the value
+//                                      streams there; both ends are within
+//                                      one link of the reader),
+//   D_j = psi(x + e_j) - psi(x - e_j)  when x + e_j is solid (the value comes
+//                                      back to x by bounce-back and only x
+//                                      reads it, so the central difference
+//                                      across the wall is available).
+// The factor 1/4 was chosen by measuring the stored error against the FP64
+// reference on porous and droplet cases.  Contraction is off here so every
+// kernel evaluates the predictor with the same roundings.
+// ---------------------------------------------------------------------------
+struct PredRef {
+    float2 p;   // predictor of both components
+    float rt;   // writer's total density (the scale)
+};
+
+// Predictor of a value written by x along direction j: rw = psi-hat(x), d =
+// the difference D_j of psi-hat (both components; component s uses the
+// other one's).
+__device__ __forceinline__ float2 pred_value(int j, float2 rw, float2 d, float G) {
+#pragma clang fp contract(off)
+    const float kG = 0.25f * G;
+    const float m0 = fmaf(-kG, d.y, 1.0f);
+    const float m1 = fmaf(-kG, d.x, 1.0f);
+    return make_float2(weight(j) * rw.x * m0, weight(j) * rw.y * m1);
+}
+
+__device__ __forceinline__ float2 psi_diff(float2 a, float2 b) {
+#pragma clang fp contract(off)
+    return make_float2(a.x - b.x, a.y - b.y);
+}
+
+// Predictor and scale of f_i as read at x: the value was written by x - e_i
+// along i, or, when x - e_i is solid (wall), by x itself along opp(i) (same
+// weight) and bounced back.  psi_rel(dx, dy, dz) = previous-level psi-hat at
+// x + (dx, dy, dz).  Both neighbours are read and the cases selected without
+// branches.
+template <class PsiRel>
+__device__ __forceinline__ PredRef pred_read(int i, bool wall, PsiRel psi_rel, float G) {
+    const float2 own = psi_rel(0, 0, 0);
+    const float2 up = psi_rel(-DX[i], -DY[i], -DZ[i]);
+    const float2 dn = psi_rel(DX[i], DY[i], DZ[i]);
+    const float2 rw = make_float2(wall ? own.x : up.x, wall ? own.y : up.y);
+    const float2 a = make_float2(wall ? up.x : own.x, wall ? up.y : own.y);
+    const float2 b = make_float2(wall ? dn.x : up.x, wall ? dn.y : up.y);
+    return PredRef{pred_value(i, rw, psi_diff(a, b), G), rw.x + rw.y};
+}
+
+// Predictor of f*_i written by x (direction i); wall: x + e_i is solid.  The
+// same expressions as pred_read at the reader.
+template <class PsiRel>
+__device__ __forceinline__ float2 pred_write(int i, bool wall, PsiRel psi_rel, float G) {
+    const float2 own = psi_rel(0, 0, 0);
+    const float2 dn = psi_rel(DX[i], DY[i], DZ[i]);
+    const float2 up = psi_rel(-DX[i], -DY[i], -DZ[i]);
+    const float2 other = make_float2(wall ? up.x : own.x, wall ? up.y : own.y);
+    return pred_value(i, own, psi_diff(dn, other), G);
+}
 
 __device__ __forceinline__ float inv_total(float2 r) {
     const float t = r.x + r.y;
@@ -229,36 +306,42 @@ __device__ __forceinline__ void load_raw(RawNode<C>& r, const Pops<C>& P, uint32
     }
 }
 
-// Decode a loaded node.  RefAt(i, solid) returns the previous-level
-// densities of the node that wrote f_i(x): x - e_i, or x itself when x - e_i
-// is solid (F16/BF16 only); nbm is the node's neighbourhood word.
-template <class C, class RefAt>
-__device__ __forceinline__ void decode_node(float (&f)[2][Q], const RawNode<C>& r, uint32_t nbm, RefAt ref_at) {
+// Decode a loaded node.  PredAt(i, wall) returns the codec predictor and
+// scale of f_i(x) (pred_read; wall: x - e_i is solid), F16/BF16 only; nbm is
+// the node's neighbourhood word.
+template <class C, class PredAt>
+__device__ __forceinline__ void decode_node(float (&f)[2][Q], const RawNode<C>& r, uint32_t nbm, PredAt pred_at) {
     f[0][0] = r.rest[0];
     f[1][0] = r.rest[1];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if constexpr (C::kRef) {
-            const float2 rw = ref_at(i, (bool)((nbm >> opp(i)) & 1u));
-            const float rt = rw.x + rw.y;
-            f[0][i] = C::dec(r.h[0][i], weight(i), rw.x, rt);
-            f[1][i] = C::dec(r.h[1][i], weight(i), rw.y, rt);
+            const PredRef q = pred_at(i, (bool)((nbm >> opp(i)) & 1u));
+            f[0][i] = C::dec(r.h[0][i], q.p.x, q.rt);
+            f[1][i] = C::dec(r.h[1][i], q.p.y, q.rt);
         } else {
-            f[0][i] = C::dec(r.h[0][i], weight(i), 0.0f, 0.0f);
-            f[1][i] = C::dec(r.h[1][i], weight(i), 0.0f, 0.0f);
+            f[0][i] = C::dec(r.h[0][i], 0.0f, 0.0f);
+            f[1][i] = C::dec(r.h[1][i], 0.0f, 0.0f);
         }
     }
 }
 
 // Load and decode the 19 incoming populations of both components at fluid
-// node k, with the previous-level densities read from the dense field rprev
-// (F16/BF16 only).
+// node k, with the previous-level pseudopotential read from the dense field
+// rprev (F16/BF16 only).
 template <class C, bool ODD, class FidAt>
 __device__ __forceinline__ void load_node(float (&f)[2][Q], const Pops<C>& P, const float2* rprev,
-                                          uint32_t nbm, const Nb& nb, uint32_t k, FidAt fid_at, int np) {
+                                          uint32_t nbm, const Nb& nb, uint32_t k, FidAt fid_at, int np, float G) {
     RawNode<C> r;
     load_raw<C, ODD, true>(r, P, k, fid_at, np);
-    decode_node<C>(f, r, nbm, [&](int i, bool solid) { return ld(rprev, solid ? nb.idx : nb.at(i, -1)); });
+    if constexpr (C::kRef) {
+        auto psi_rel = [&](int dx, int dy, int dz) {
+            return ld(rprev, nb.idx + (uint32_t)(nb.ox[1 + dx] + nb.oy[1 + dy] + nb.oz[1 + dz]));
+        };
+        decode_node<C>(f, r, nbm, [&](int i, bool wall) { return pred_read(i, wall, psi_rel, G); });
+    } else {
+        decode_node<C>(f, r, nbm, [&](int, bool) { return PredRef{make_float2(0.f, 0.f), 0.f}; });
+    }
 }
 
 // Sum of populations in a fixed order (shared by every kernel that needs the
@@ -278,18 +361,18 @@ __device__ __forceinline__ float sum19(const float (&f)[Q]) {
 // stored mass equal to rho to FP32 round-off: no bias from the FP32 weights
 // not summing exactly to 1, and the FP16/BF16 rounding of the moving
 // populations is absorbed by the FP32 rest population.
-// mass: incoming component densities; rho_ref: this node's density as the
-// decoder will read it next step (F16/BF16 codecs only).
-template <class C, bool ODD, bool WIDE, class FidAt>
+// mass: incoming component densities; PredW(i) returns the codec predictor
+// of f*_i (pred_write), rt and inv_rt this node's previous-level total
+// density and its inverse (F16/BF16 codecs only).
+template <class C, bool ODD, bool WIDE, class FidAt, class PredW>
 __device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C>& D, const float (&mass)[2],
-                                           float2 rho_ref, uint32_t k, FidAt fid_at, int np) {
+                                           PredW pred_w, float rt, float inv_rt, uint32_t k, FidAt fid_at, int np) {
     float sum0 = 0.0f, sum1 = 0.0f;
-    const float inv_t = C::kRef ? inv_total(rho_ref) : 0.0f;
-    const float rt = rho_ref.x + rho_ref.y;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const typename C::T h0 = C::enc(fs[0][i], weight(i), rho_ref.x, inv_t);
-        const typename C::T h1 = C::enc(fs[1][i], weight(i), rho_ref.y, inv_t);
+        const float2 pr = C::kRef ? pred_w(i) : make_float2(0.f, 0.f);
+        const typename C::T h0 = C::enc(fs[0][i], pr.x, inv_rt);
+        const typename C::T h1 = C::enc(fs[1][i], pr.y, inv_rt);
         const typename Pops<C>::P2 hp{{h0, h1}};
         if constexpr (!ODD) {
             st_pop<WIDE>(D.plane(opp(i), np), k, hp);
@@ -301,8 +384,8 @@ __device__ __forceinline__ void store_node(const float (&fs)[2][Q], const Pops<C
             const uint32_t e = wall ? k + ((i & 1) ? (uint32_t)np : 0u) : (uint32_t)dst + ((i & 1) ? 0u : (uint32_t)np);
             st_pop<WIDE>(D.plane(lo, np), e, hp);
         }
-        sum0 += C::dec(h0, weight(i), rho_ref.x, rt);
-        sum1 += C::dec(h1, weight(i), rho_ref.y, rt);
+        sum0 += C::dec(h0, pr.x, rt);
+        sum1 += C::dec(h1, pr.y, rt);
     }
     st_pop<WIDE>(D.rests(), k, Pair<float>{{mass[0] - sum0, mass[1] - sum1}});
 }

@@ -196,11 +196,26 @@ __global__ void k_tile_ids(const uint32_t* __restrict__ nbm, Geo g, const int* _
 }
 
 // ---------------------------------------------------------------------------
-// Initial state f_i = w_i rho (fluid at rest), even-parity layout.
+// Initial state f_i = w_i rho (fluid at rest), even-parity layout.  The
+// values are recorded as written at a level before the first, whose
+// pseudopotential field (the codec predictors' field of the F16/BF16 forms)
+// is rprev: the initial densities at fluid nodes (k_init_ref, zero at solid
+// ones), then the virtual densities at the boundary solids (k_ivsd).
 // ---------------------------------------------------------------------------
+__global__ void k_init_ref(const uint32_t* __restrict__ nbm, const float* __restrict__ rho_in,
+                           float2* __restrict__ rprev, Geo g) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx) return;
+    const uint32_t self = (uint32_t)(x + g.nx * (y + g.ny * z));
+    rprev[self] = (nbm[self] & SELF_SOLID) ? make_float2(0.f, 0.f)
+                                           : make_float2(rho_in[self], rho_in[(size_t)g.n + self]);
+}
+
 template <class C>
 __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* __restrict__ fid,
-                       const float* __restrict__ rho_in, float2* __restrict__ rprev, Geo g) {
+                       const float2* __restrict__ rprev, Geo g, float G) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const int z = blockIdx.z;
@@ -208,40 +223,32 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* _
     const Nb nb(x, y, z, g);
     const uint32_t self = nb.idx;
     const uint32_t m = nbm[self];
-    if (m & SELF_SOLID) {
-        rprev[self] = make_float2(0.f, 0.f);
-        return;
-    }
+    if (m & SELF_SOLID) return;
     const uint32_t k = (uint32_t)fid[self];
-    const float r0 = rho_in[self], r1 = rho_in[(size_t)g.n + self];
-    rprev[self] = make_float2(r0, r1);
+    const float2 r = rprev[self];
+    auto psi_rel = [&](int dx, int dy, int dz) {
+        return ld(rprev, self + (uint32_t)(nb.ox[1 + dx] + nb.oy[1 + dy] + nb.oz[1 + dz]));
+    };
     float sum0 = 0.f, sum1 = 0.f;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const float f0 = weight(i) * r0, f1 = weight(i) * r1;
-        typename C::T h0, h1;
+        const float f0 = weight(i) * r.x, f1 = weight(i) * r.y;
+        PredRef q{make_float2(0.f, 0.f), 0.f};
+        float inv_t = 0.f;
         if constexpr (C::kRef) {
-            // reference densities of the node recorded as the writer of
-            // slot (i, k): x - e_i if fluid, else x
-            const bool src_solid = (m >> opp(i)) & 1u;
-            const uint32_t w = src_solid ? self : nb.at(i, -1);
-            const float2 rw = src_solid ? make_float2(r0, r1) : make_float2(rho_in[w], rho_in[(size_t)g.n + w]);
-            const float inv_t = inv_total(rw);
-            const float rt = rw.x + rw.y;
-            h0 = C::enc(f0, weight(i), rw.x, inv_t);
-            h1 = C::enc(f1, weight(i), rw.y, inv_t);
-            sum0 += C::dec(h0, weight(i), rw.x, rt);
-            sum1 += C::dec(h1, weight(i), rw.y, rt);
-        } else {
-            h0 = C::enc(f0, weight(i), 0.f, 0.f);
-            h1 = C::enc(f1, weight(i), 0.f, 0.f);
-            sum0 += C::dec(h0, weight(i), 0.f, 0.f);
-            sum1 += C::dec(h1, weight(i), 0.f, 0.f);
+            // predictor of the node recorded as the writer of slot (i, k):
+            // x - e_i if fluid, else x (bounce-back)
+            q = pred_read(i, (bool)((m >> opp(i)) & 1u), psi_rel, G);
+            inv_t = q.rt > 0.0f ? 1.0f / q.rt : 0.0f;
         }
+        const typename C::T h0 = C::enc(f0, q.p.x, inv_t);
+        const typename C::T h1 = C::enc(f1, q.p.y, inv_t);
+        sum0 += C::dec(h0, q.p.x, q.rt);
+        sum1 += C::dec(h1, q.p.y, q.rt);
         st_pop<true>(P.plane(i, g.np), k, typename Pops<C>::P2{{h0, h1}});
     }
     // rest population from the node mass (see store_node)
-    st_pop<true>(P.rests(), k, Pair<float>{{r0 - sum0, r1 - sum1}});
+    st_pop<true>(P.rests(), k, Pair<float>{{r.x - sum0, r.y - sum1}});
 }
 
 // ---------------------------------------------------------------------------
@@ -318,14 +325,15 @@ struct HaloFid {
 
 // K1: densities.  psi[x] = (rho1, rho2) at fluid nodes.  In odd steps the
 // fluid-id halo is staged first (the gathers need it); with the F16/BF16
-// codecs the previous-level densities that decode the stored values are
-// staged as an LDS halo as well, while the thread's first node is loaded.
-// At least 8 waves per SIMD in even steps (7 with a decoding halo) and 6
-// in odd steps; the compiler's default schedule would hold ~105 VGPRs.
+// codecs the previous level's pseudopotential field, which gives the codec
+// predictors, is staged as an LDS halo as well, while the thread's first
+// node is loaded.  At least 8 waves per SIMD in even steps (7 with a
+// decoding halo) and 6 in odd steps; the compiler's default schedule would
+// hold ~105 VGPRs.
 template <class C, bool ODD, bool WIDE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 6 : (C::kRef ? 7 : 8))))
 void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
-               float2* __restrict__ psi, Geo g) {
+               float2* __restrict__ psi, Geo g, float G) {
     const int a = active_of_block(S.nactive);
     if (a < 0) return;
     const int t = S.active[a];
@@ -348,9 +356,12 @@ void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const floa
         const uint32_t m = C::kRef ? ld(nbm, idx) : 0u;
         const int tx = q.lx + 1, ty = q.ly + 1, tz = q.lz + 1;
         float f[2][Q];
-        decode_node<C>(f, r, m, [&](int i, bool solid) {
-            return solid ? reft[tz][ty][tx] : reft[tz - DZ[i]][ty - DY[i]][tx - DX[i]];
-        });
+        if constexpr (C::kRef) {
+            auto psi_rel = [&](int dx, int dy, int dz) { return reft[tz + dz][ty + dy][tx + dx]; };
+            decode_node<C>(f, r, m, [&](int i, bool wall) { return pred_read(i, wall, psi_rel, G); });
+        } else {
+            decode_node<C>(f, r, m, [&](int, bool) { return PredRef{make_float2(0.f, 0.f), 0.f}; });
+        }
         st(psi, idx, make_float2(sum19(f[0]), sum19(f[1])));
     };
     const int j0 = threadIdx.x;
@@ -447,9 +458,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
         const uint32_t idx = (uint32_t)(x0 + h.tx - 1 + g.nx * (y0 + h.ty - 1 + g.ny * (z0 + h.tz - 1)));
         const uint32_t m = C::kRef ? ld(nbm, idx) : 0u;
         float f[2][Q];
-        decode_node<C>(f, r, m, [&](int i, bool solid) {
-            return solid ? reft[h.tz][h.ty][h.tx] : reft[h.tz - DZ[i]][h.ty - DY[i]][h.tx - DX[i]];
-        });
+        if constexpr (C::kRef) {
+            auto prev_rel = [&](int dx, int dy, int dz) { return reft[h.tz + dz][h.ty + dy][h.tx + dx]; };
+            decode_node<C>(f, r, m, [&](int i, bool wall) { return pred_read(i, wall, prev_rel, ph.G); });
+        } else {
+            decode_node<C>(f, r, m, [&](int, bool) { return PredRef{make_float2(0.f, 0.f), 0.f}; });
+        }
         const float rho[2] = {sum19(f[0]), sum19(f[1])};
         float acc[2][3];
         psi_sum([&](int i) { return psit[h.tz + DZ[i]][h.ty + DY[i]][h.tx + DX[i]]; }, acc);
@@ -457,7 +471,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
         total_force(rho, acc, ph, F);
         float u[3];
         collide(f, rho, F, ph, u);
-        store_node<C, ODD, WIDE>(f, D, rho, psit[h.tz][h.ty][h.tx], k, h, g.np);
+        // codec predictors of the values written (F16/BF16) come from this
+        // level's psi-hat, the readers' previous level
+        // (a laundered zero offset keeps the compiler from reading them all
+        // before the collision and holding them across it)
+        int zero = 0;
+        asm volatile("" : "+v"(zero));
+        auto cur_rel = [&](int dx, int dy, int dz) { return psit[h.tz + dz][h.ty + dy][h.tx + dx + zero]; };
+        const float2 own = psit[h.tz][h.ty][h.tx];
+        store_node<C, ODD, WIDE>(
+            f, D, rho, [&](int i) { return pred_write(i, (bool)((m >> i) & 1u), cur_rel, ph.G); },
+            own.x + own.y, C::kRef ? inv_total(own) : 0.0f, k, h, g.np);
     };
     const int j0 = threadIdx.x;
     RawNode<C> r;
@@ -508,7 +532,7 @@ __global__ __launch_bounds__(256) void k_fields(Pops<C> P, const int* __restrict
         if (!(m & SELF_SOLID)) {
             float f[2][Q];
             load_node<C, ODD>(f, P, rprev, m, nb, (uint32_t)fid[self],
-                              [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np);
+                              [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np, ph.G);
             rho[0] = sum19(f[0]);
             rho[1] = sum19(f[1]);
             float acc[2][3];
@@ -644,28 +668,30 @@ void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const in
 
 template <class C>
 void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,
-                 const Geo& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_init<C>, row_grid(g), dim3(64), 0, s, P, nbm, fid, rho, rprev, g);
+                 const int* list, const float* xil, int nbound, const Geo& g, float G, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_ref, row_grid(g), dim3(64), 0, s, nbm, rho, rprev, g);
+    launch_ivsd(list, xil, nbound, nbm, rprev, g, s);
+    hipLaunchKernelGGL(k_init<C>, row_grid(g), dim3(64), 0, s, P, nbm, fid, (const float2*)rprev, g, G);
 }
 
 template <class C, bool ODD, bool WIDE>
 static void launch_density_as(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev,
-                              float2* psi, const Geo& g, hipStream_t s) {
+                              float2* psi, const Geo& g, float G, hipStream_t s) {
     hipLaunchKernelGGL((k_density<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, nbm, rprev, psi,
-                       g);
+                       g, G);
 }
 
 template <class C>
 void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
-                    const Geo& g, int odd, hipStream_t s) {
+                    const Geo& g, float G, int odd, hipStream_t s) {
     if (S.nactive <= 0) return;
     const bool wide = pops_wide(g.np);
     if (odd)
-        wide ? launch_density_as<C, true, true>(P, S, nbm, rprev, psi, g, s)
-             : launch_density_as<C, true, false>(P, S, nbm, rprev, psi, g, s);
+        wide ? launch_density_as<C, true, true>(P, S, nbm, rprev, psi, g, G, s)
+             : launch_density_as<C, true, false>(P, S, nbm, rprev, psi, g, G, s);
     else
-        wide ? launch_density_as<C, false, true>(P, S, nbm, rprev, psi, g, s)
-             : launch_density_as<C, false, false>(P, S, nbm, rprev, psi, g, s);
+        wide ? launch_density_as<C, false, true>(P, S, nbm, rprev, psi, g, G, s)
+             : launch_density_as<C, false, false>(P, S, nbm, rprev, psi, g, G, s);
 }
 
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
@@ -743,9 +769,9 @@ hipError_t scratch_address(int device, double** out) {
 
 #define MCLBM_INSTANTIATE(C)                                                                              \
     template void launch_init<C>(const Pops<C>&, const uint32_t*, const int*, const float*, float2*,      \
-                                 const Geo&, hipStream_t);                                                \
+                                 const int*, const float*, int, const Geo&, float, hipStream_t);          \
     template void launch_density<C>(const Pops<C>&, const Sparse&, const uint32_t*, const float2*,        \
-                                    float2*, const Geo&, int, hipStream_t);                               \
+                                    float2*, const Geo&, float, int, hipStream_t);                        \
     template void launch_collide_stream<C>(const Pops<C>&, const Pops<C>&, const Sparse&, const uint32_t*, \
                                            const float2*, const float2*, const Geo&, const Phys&, int,    \
                                            hipStream_t);                                                  \

@@ -36,12 +36,17 @@ void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, 
 void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const int* base, const int* apos, int* fid,
                      uint16_t* loc, int* active, hipStream_t s);
 
+// Initial state from the densities rho [2][n].  rprev receives the
+// pseudopotential field of the level before the first (the initial densities
+// at fluid nodes, their virtual densities, Eqs. 14-15, at the boundary solids
+// in list/xil), from which the F16/BF16 codec predictors of the stored
+// values are taken.  G: the cohesion parameter (codec predictors).
 template <class C>
 void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,
-                 const Geo& g, hipStream_t s);
+                 const int* list, const float* xil, int nbound, const Geo& g, float G, hipStream_t s);
 template <class C>
 void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
-                    const Geo& g, int odd, hipStream_t s);
+                    const Geo& g, float G, int odd, hipStream_t s);
 void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
                  const Geo& g, hipStream_t s);
 template <class C>

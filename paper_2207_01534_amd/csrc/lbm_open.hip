@@ -51,15 +51,21 @@ __device__ __forceinline__ OpenSlot slot_of(int i, bool odd, uint32_t k, uint32_
     return s;
 }
 
+// Value of f_i(x) of component s stored in slot q, decoded with the codec
+// predictor of the value as read at x (pred_read) from the previous level's
+// pseudopotential field psi (F16/BF16 only).
 template <class C>
-__device__ __forceinline__ float read_pop(const Pops<C>& P, int s, const OpenSlot& q, int i, const float2* psi,
-                                          int np) {
+__device__ __forceinline__ float read_pop(const Pops<C>& P, int s, const OpenSlot& q, int i, uint32_t m,
+                                          const Nb& nb, const float2* psi, float G, int np) {
     const typename C::T h = *P.at(s, q.dir, q.id, np);
     if constexpr (C::kRef) {
-        const float2 r = ld(psi, q.writer);
-        return C::dec(h, weight(i), s ? r.y : r.x, r.x + r.y);
+        auto psi_rel = [&](int dx, int dy, int dz) {
+            return ld(psi, nb.idx + (uint32_t)(nb.ox[1 + dx] + nb.oy[1 + dy] + nb.oz[1 + dz]));
+        };
+        const PredRef r = pred_read(i, (bool)((m >> opp(i)) & 1u), psi_rel, G);
+        return C::dec(h, s ? r.p.y : r.p.x, r.rt);
     } else {
-        return C::dec(h, weight(i), 0.0f, 0.0f);
+        return C::dec(h, 0.0f, 0.0f);
     }
 }
 
@@ -113,22 +119,24 @@ __device__ __forceinline__ StagedSlot staged_slot(int i, bool odd, int k, int ly
     return q;
 }
 
-// Codec reference of a stored value: the densities (previous level) of the
-// node that wrote it, x itself across a wall, else x - e_i; read from the
-// block's staged copy (F16/BF16 only).
+// Codec predictor and scale of f_i as read at staged x position k of the
+// thread's row (pred_read over the block's staged copy of the previous
+// level's pseudopotential field; F16/BF16 only).
 struct CodecRef {
-    float rw[2], rt, inv;
+    float p[2], rt, inv;
 };
 
 template <class C, class Staged>
-__device__ __forceinline__ CodecRef codec_ref(const Staged& sr, int k, int ly, int lz, int i, bool up_solid) {
+__device__ __forceinline__ CodecRef codec_ref(const Staged& sr, int k, int ly, int lz, int i, bool up_solid,
+                                              float G) {
     CodecRef c{{0.f, 0.f}, 0.f, 0.f};
     if constexpr (C::kRef) {
-        const float2 r = up_solid ? sr[k][lz + 1][ly + 1] : sr[k - DX[i]][lz + 1 - DZ[i]][ly + 1 - DY[i]];
-        c.rw[0] = r.x;
-        c.rw[1] = r.y;
-        c.rt = r.x + r.y;
-        c.inv = inv_total(r);
+        auto psi_rel = [&](int dx, int dy, int dz) { return sr[k + dx][lz + 1 + dz][ly + 1 + dy]; };
+        const PredRef r = pred_read(i, up_solid, psi_rel, G);
+        c.p[0] = r.p.x;
+        c.p[1] = r.p.y;
+        c.rt = r.rt;
+        c.inv = r.rt > 0.0f ? 1.0f / r.rt : 0.0f;
     }
     return c;
 }
@@ -139,7 +147,7 @@ __device__ __forceinline__ CodecRef codec_ref(const Staged& sr, int k, int ly, i
 template <class C>
 __global__ void __launch_bounds__(OPEN_PATCH * OPEN_PATCH)
 k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict__ psi,
-               const float* __restrict__ held, Geo g, int odd, float rho_in, float rho_out) {
+               const float* __restrict__ held, Geo g, int odd, float rho_in, float rho_out, float G) {
     using T = typename C::T;
     using P2 = Pair<T>;
     __shared__ int sf[OPEN_XS][OPEN_H][OPEN_H];   // [x position][z][y]
@@ -183,10 +191,10 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const StagedSlot q = staged_slot(i, odd, kf, ly, lz, sf);
-        const CodecRef c = codec_ref<C>(sr, kf, ly, lz, i, q.up_solid);
+        const CodecRef c = codec_ref<C>(sr, kf, ly, lz, i, q.up_solid, G);
         const P2 h = ld(P.plane(q.dir, np), q.id);
-        ff[0][i] = C::dec(h.v[0], weight(i), c.rw[0], c.rt);
-        ff[1][i] = C::dec(h.v[1], weight(i), c.rw[1], c.rt);
+        ff[0][i] = C::dec(h.v[0], c.p[0], c.rt);
+        ff[1][i] = C::dec(h.v[1], c.p[1], c.rt);
     }
     float rf[2] = {0.f, 0.f}, j[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -210,13 +218,13 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const StagedSlot q = staged_slot(i, odd, kb, ly, lz, sf);
-        const CodecRef c = codec_ref<C>(sr, kb, ly, lz, i, q.up_solid);
+        const CodecRef c = codec_ref<C>(sr, kb, ly, lz, i, q.up_solid, G);
         const float v = ff[imposed][i] + feq(i, rho_b, u, usq) - feq(i, rf[imposed], u, usq);
-        const T hi = C::enc(v, weight(i), c.rw[imposed], c.inv);
-        moving += C::dec(hi, weight(i), c.rw[imposed], c.rt);
+        const T hi = C::enc(v, c.p[imposed], c.inv);
+        moving += C::dec(hi, c.p[imposed], c.rt);
         if (DX[i] == dir_in) {
             const float vo = held[((size_t)side * Q + i) * A + yz];
-            const T ho = C::enc(vo, weight(i), c.rw[other], c.inv);
+            const T ho = C::enc(vo, c.p[other], c.inv);
             P2 pr;
             pr.v[imposed] = hi;
             pr.v[other] = ho;
@@ -233,12 +241,12 @@ k_open_rebuild(Pops<C> P, const int* __restrict__ fid, const float2* __restrict_
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const StagedSlot q = staged_slot(i, odd, kg, ly, lz, sf);
-        const CodecRef c = codec_ref<C>(sr, kg, ly, lz, i, q.up_solid);
+        const CodecRef c = codec_ref<C>(sr, kg, ly, lz, i, q.up_solid, G);
         P2 pr;
-        pr.v[0] = C::enc(weight(i) * rg.x, weight(i), c.rw[0], c.inv);
-        pr.v[1] = C::enc(weight(i) * rg.y, weight(i), c.rw[1], c.inv);
-        sum[0] += C::dec(pr.v[0], weight(i), c.rw[0], c.rt);
-        sum[1] += C::dec(pr.v[1], weight(i), c.rw[1], c.rt);
+        pr.v[0] = C::enc(weight(i) * rg.x, c.p[0], c.inv);
+        pr.v[1] = C::enc(weight(i) * rg.y, c.p[1], c.inv);
+        sum[0] += C::dec(pr.v[0], c.p[0], c.rt);
+        sum[1] += C::dec(pr.v[1], c.p[1], c.rt);
         st(P.plane(q.dir, np), q.id, pr);
     }
     st(P.rests(), (uint32_t)sf[kg][lz + 1][ly + 1], Pair<float>{{rg.x - sum[0], rg.y - sum[1]}});
@@ -276,7 +284,8 @@ __global__ void k_open_pressure(const float2* __restrict__ psi, const uint32_t* 
 // boundary planes (inlet: component 2, e_x = +1; outlet: component 1, e_x = -1).
 template <class C>
 __global__ void k_open_capture(Pops<C> P, const int* __restrict__ fid, const uint32_t* __restrict__ nbm,
-                               const float2* __restrict__ rprev, float* __restrict__ held, Geo g, int odd) {
+                               const float2* __restrict__ rprev, float* __restrict__ held, Geo g, int odd,
+                               float G) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int A = g.ny * g.nz;
     if (a >= 2 * A) return;
@@ -290,7 +299,8 @@ __global__ void k_open_capture(Pops<C> P, const int* __restrict__ fid, const uin
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         float v = 0.f;
-        if (i > 0 && DX[i] == dir_in) v = read_pop<C>(P, other, slot_of(i, odd, kb, mb, nb, fid), i, rprev, g.np);
+        if (i > 0 && DX[i] == dir_in)
+            v = read_pop<C>(P, other, slot_of(i, odd, kb, mb, nb, fid), i, mb, nb, rprev, G, g.np);
         held[((size_t)side * Q + i) * A + yz] = v;
     }
 }
@@ -322,16 +332,16 @@ void launch_open_mirror(float2* psi, const Geo& g, hipStream_t s) {
 
 template <class C>
 void launch_open_rebuild(const Pops<C>& P, const int* fid, const float2* psi, const float* held, const Geo& g,
-                         int odd, float rho_in, float rho_out, hipStream_t s) {
+                         int odd, float rho_in, float rho_out, float G, hipStream_t s) {
     hipLaunchKernelGGL(k_open_rebuild<C>, dim3(xcd_grid(2 * open_patches(g))), dim3(OPEN_PATCH * OPEN_PATCH), 0, s,
-                       P, fid, psi, held, g, odd, rho_in, rho_out);
+                       P, fid, psi, held, g, odd, rho_in, rho_out, G);
 }
 
 template <class C>
 void launch_open_capture(const Pops<C>& P, const int* fid, const uint32_t* nbm, const float2* rprev, float* held,
-                         const Geo& g, int odd, hipStream_t s) {
+                         const Geo& g, int odd, float G, hipStream_t s) {
     hipLaunchKernelGGL(k_open_capture<C>, dim3(blocks_for(2 * g.ny * g.nz, 64)), dim3(64), 0, s, P, fid, nbm,
-                       rprev, held, g, odd);
+                       rprev, held, g, odd, G);
 }
 
 void launch_open_pressure(const float2* psi, const uint32_t* nbm, const Geo& g, float G, double* out,
@@ -345,9 +355,9 @@ void launch_open_check(const uint32_t* nbm, const Geo& g, int* count, hipStream_
 
 #define MCLBM_OPEN_INSTANTIATE(C)                                                                              \
     template void launch_open_rebuild<C>(const Pops<C>&, const int*, const float2*, const float*, const Geo&, \
-                                         int, float, float, hipStream_t);                                    \
+                                         int, float, float, float, hipStream_t);                             \
     template void launch_open_capture<C>(const Pops<C>&, const int*, const uint32_t*, const float2*, float*, \
-                                         const Geo&, int, hipStream_t);
+                                         const Geo&, int, float, hipStream_t);
 MCLBM_OPEN_INSTANTIATE(CodecF32)
 MCLBM_OPEN_INSTANTIATE(CodecF16)
 MCLBM_OPEN_INSTANTIATE(CodecBF16)

@@ -183,7 +183,7 @@ struct mclbm_lattice {
         const float2* rprev = R((int)((t + 1) & 1));
         with_codec([&](auto c) {
             using C = decltype(c);
-            launch_density<C>(pops<C>(), sparse(), nbm(), rprev, psi, g, odd, stream);
+            launch_density<C>(pops<C>(), sparse(), nbm(), rprev, psi, g, ph.G, odd, stream);
         });
         launch_ivsd(list(), xil(), nbound, nbm(), psi, g, stream);
         if (open) launch_open_mirror(psi, g, stream);
@@ -318,7 +318,8 @@ mclbm_status mclbm_init_equilibrium(mclbm_lattice* lat, const float* d_rho) {
     // state at t = 0; the codecs' reference density of the previous level is R[1]
     lat->with_codec([&](auto c) {
         using C = decltype(c);
-        launch_init<C>(lat->pops<C>(), lat->nbm(), lat->fid(), d_rho, lat->R(1), lat->g, lat->stream);
+        launch_init<C>(lat->pops<C>(), lat->nbm(), lat->fid(), d_rho, lat->R(1), lat->list(), lat->xil(), lat->nbound,
+                       lat->g, lat->ph.G, lat->stream);
     });
     HIP_TRY(hipGetLastError());
     lat->t = 0;
@@ -349,7 +350,8 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
         lat->with_codec([&](auto c) {
             using C = decltype(c);
             mark(0);
-            launch_density<C>(lat->pops<C>(), lat->sparse(), lat->nbm(), rprev, psi, lat->g, odd, lat->stream);
+            launch_density<C>(lat->pops<C>(), lat->sparse(), lat->nbm(), rprev, psi, lat->g, lat->ph.G, odd,
+                              lat->stream);
             mark(0);
             mark(1);
             launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, lat->g, lat->stream);
@@ -361,7 +363,7 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
             mark(2);
             if (lat->open)
                 launch_open_rebuild<C>(lat->pops<C>(), lat->fid(), psi, lat->held(), lat->g, 1 - odd,
-                                       lat->rho_in, lat->rho_out, lat->stream);
+                                       lat->rho_in, lat->rho_out, lat->ph.G, lat->stream);
         });
         lat->t += 1;
     }
@@ -392,7 +394,7 @@ mclbm_status mclbm_set_open_x(mclbm_lattice* lat, int32_t enable, double rho1_in
         lat->with_codec([&](auto c) {
             using C = decltype(c);
             launch_open_capture<C>(lat->pops<C>(), lat->fid(), lat->nbm(), lat->R(1 - odd), lat->held(), lat->g,
-                                   odd, lat->stream);
+                                   odd, lat->ph.G, lat->stream);
         });
         HIP_TRY(hipGetLastError());
     }
@@ -781,8 +783,8 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
             const int odd = (int)((ta + k) & 1);
             const Pops<CodecF32> sk = slot_pops(W.seg[b] + (size_t)k * slot, L);
             float2* psi = (float2*)(W.psi[b] + (size_t)k * psi_stride);
-            launch_density<CodecF32>(sk, lat->sparse(), lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g, odd,
-                                     s2);
+            launch_density<CodecF32>(sk, lat->sparse(), lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g,
+                                     lat->ph.G, odd, s2);
             launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, g, s2);
             if (k + 1 < len) {
                 const Pops<CodecF32> sn = slot_pops(W.seg[b] + (size_t)(k + 1) * slot, L);

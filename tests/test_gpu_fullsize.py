@@ -28,8 +28,9 @@ TAU, G = (1.5, 0.6), 3.5
 # (e_rho, e_u), field-max normalised.  FP32 velocity: the momentum is a sum of
 # 38 populations of size ~w rho, so its FP32 round-off is ~1e-7 absolute; at
 # t = 3 quiescent windows have |u| ~ 1e-3, which puts the normalised floor
-# near 1e-4, hence 2e-4.  FP16: the storage gate.
-BAR = {"f32": (1e-5, 2e-4), "f16": (2e-3, 2e-3)}
+# near 1e-4, hence 2e-4.  FP16: the storage gate (1.5e-3, a margin below the
+# 2e-3 target).
+BAR = {"f32": (1e-5, 2e-4), "f16": (1.5e-3, 1.5e-3)}
 
 
 def _index(starts, dims):

@@ -1,9 +1,10 @@
 """FP16 / BF16 offset storage against the FP64 oracle (arithmetic stays FP32).
 
-Bars: FP16 storage -- density and velocity errors <= 2e-3 (normalised by the
-field maxima) and relative mass drift <= 1e-6 after 200 steps; BF16 is
-reported with a looser sanity bound.  The error table printed by each case is
-the per-field record for the storage forms."""
+Bars: FP16 storage -- density and velocity errors <= 1.5e-3 (normalised by the
+field maxima; the target is 2e-3, the bar keeps a margin below it) and
+relative mass drift <= 1e-6 after 200 steps; BF16 is reported with a looser
+sanity bound.  The error table printed by each case is the per-field record
+for the storage forms."""
 import numpy as np
 import pytest
 
@@ -13,16 +14,9 @@ from parity_util import field_errors, gpu_case, gpu_fields, oracle_case, oracle_
 
 pytestmark = pytest.mark.gpu
 
-BARS = {1: dict(e_rho=2e-3, e_u=2e-3, drift=1e-6),      # FP16
+BARS = {1: dict(e_rho=1.5e-3, e_u=1.5e-3, drift=1e-6),  # FP16
         2: dict(e_rho=2e-2, e_u=5e-2, drift=1e-6),      # BF16 (reported; sanity bound only)
         0: dict(e_rho=1e-5, e_u=1e-4, drift=1e-6)}      # FP32 reference row
-# The sphere-pack drainage moves a sharp front at G = 3.5: there the stored
-# offset is dominated by the forcing term 3 w_i e_i.F of Eq. (9), and FP16's
-# 11-bit significand bounds the velocity error near 2e-3 of the peak velocity
-# (measured 1.8e-3 to 2.2e-3 across kernel versions, which change the FP32
-# rounding order).  That case is reported against a 3e-3 bound; the 2e-3
-# target applies to the droplet and to the Gaussian-field medium.
-FRONT_U_BOUND = 3e-3
 NAMES = {0: "f32", 1: "f16", 2: "bf16"}
 
 
@@ -48,9 +42,7 @@ def test_storage_error_table(name, shape, storage):
     print(f"[error-table] {name} {w.shape} {NAMES[storage]}: e_rho={e['e_rho']:.3e} "
           f"rel_node={e['rel_node']:.3e} e_u={e['e_u']:.3e} e_F={e['e_F']:.3e} e_P={e['e_P']:.3e} "
           f"mass_drift={drift:.3e}", flush=True)
-    bar = dict(BARS[storage])
-    if storage == 1 and name == "spheres128":
-        bar["e_u"] = FRONT_U_BOUND
+    bar = BARS[storage]
     assert e["e_rho"] <= bar["e_rho"], e
     assert e["e_u"] <= bar["e_u"], e
     assert drift <= bar["drift"], drift
@@ -78,6 +70,6 @@ def test_fp16_full_size_gauss256_against_fp32():
               f"mass_drift={drift:.3e} S_w={d['S_w']:.6f} (f32 {d_ref['S_w']:.6f})", flush=True)
         assert drift <= 1e-6
         if storage == 1:
-            assert e_rho <= 2e-3 and e_u <= 2e-3
+            assert e_rho <= 1.5e-3 and e_u <= 1.5e-3
         del lat
         torch.cuda.synchronize()
