@@ -158,7 +158,7 @@ def test_laplace_law_surface_tension(taus):
     assert abs(icpt) < 0.05 * dp.max()
 
 
-def _wall_drop_angle(xi0, nx=120, ny=60, R0=22, steps=8000):
+def _wall_drop_angle(xi0, nx=120, ny=60, R0=22, steps=8000, tau=(1.0, 1.0)):
     """Half-drop of component 1 on a flat wall; angle through component 2 (the 'water')."""
     shape = (nx, ny, 1)
     solid = np.zeros((1, ny, nx), np.uint8)
@@ -169,7 +169,7 @@ def _wall_drop_angle(xi0, nx=120, ny=60, R0=22, steps=8000):
     rho = wl.tanh_droplet(shape, R0, center=((nx - 1) / 2, 0.5, 0.0), rho_in=lv["rho_in"],
                           rho_out=lv["rho_out"], width=lv["W"])
     rho[:, solid != 0] = 0
-    o = Oracle(OracleParams(shape, tau=(1.0, 1.0), G=3.5), solid, xi)
+    o = Oracle(OracleParams(shape, tau=tau, G=3.5), solid, xi)
     o.init_equilibrium(rho)
     o.run(steps)
     r, _, _, _ = o.fields()
@@ -206,3 +206,14 @@ def test_contact_angle_matches_paper_cubic(xi0):
     assert theta == pytest.approx(expect, abs=4.0)
     spot = PAPER["contact_angle_spot"]["xi_%g" % xi0]
     assert theta == pytest.approx(spot, abs=6.0)
+
+
+def test_xi_for_45_degrees_recalibrated_at_viscosity_ratio_10():
+    """The porous workloads run at M = 10 (tau = 1.5, 0.6) with the wetting
+    phase at a 45 degree contact angle.  The flat-wall half drop at that M
+    reaches 45 degrees at the recalibrated xi (workloads.XI45_M10); the root of
+    the paper's Sec. 3.2 cubic (fitted at M = 25 on a 3D drop) lands about
+    5 degrees higher on this quasi-2D drop."""
+    theta = _wall_drop_angle(wl.XI45_M10, tau=(1.5, 0.6))
+    assert theta == pytest.approx(45.0, abs=1.0)
+    assert wl.xi_for_angle(45.0) == pytest.approx(-0.426, abs=1e-3)
