@@ -175,8 +175,13 @@ __global__ void k_tile_count(const uint32_t* __restrict__ nbm, Geo g, int* __res
     }
 }
 
-// Fluid ids (tile base + rank inside the tile, x fastest), the dense id map
-// (-1 at solid) and each fluid node's position inside its tile.
+// Fluid ids (tile base + rank inside the tile), the dense id map (-1 at
+// solid) and each fluid node's position inside its tile.  Ranks run x
+// fastest, except that the nodes on the planes x = 0, 1, 2 and nx-3, nx-2,
+// nx-1 (the ghost, boundary and next planes when x is opened) come first, in
+// (z, y, x) order: the open-plane rebuild then finds the three nodes of each
+// of a tile's rows in consecutive slots, and a tile's rows one after the
+// other, instead of one short run per row.
 __global__ void k_tile_ids(const uint32_t* __restrict__ nbm, Geo g, const int* __restrict__ base,
                            const int* __restrict__ cnt, const int* __restrict__ active_pos,
                            int* __restrict__ fid, uint16_t* __restrict__ loc, int* __restrict__ active) {
@@ -187,8 +192,12 @@ __global__ void k_tile_ids(const uint32_t* __restrict__ nbm, Geo g, const int* _
     const bool inside = x < g.nx && y < g.ny && z < g.nz;
     const int idx = x + g.nx * (y + g.ny * z);
     const bool fluid = inside && !(nbm[idx] & SELF_SOLID);
-    int c;
-    const int rank = block_rank(fluid, wave_off, &c);
+    const bool edge = x < 3 || x >= g.nx - 3;
+    int c_edge, c;
+    const int rank_edge = block_rank(fluid && edge, wave_off, &c_edge);
+    __syncthreads();   // wave_off is reused
+    const int rank_rest = block_rank(fluid && !edge, wave_off, &c);
+    const int rank = edge ? rank_edge : c_edge + rank_rest;
     if (inside) fid[idx] = fluid ? base[blockIdx.x] + rank : -1;
     if (fluid) loc[base[blockIdx.x] + rank] = (uint16_t)(threadIdx.x + TX * (threadIdx.y + TY * threadIdx.z));
     if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0 && cnt[blockIdx.x] > 0)

@@ -2,7 +2,7 @@
 // adjoint: the lattice is cut into tiles of 64 x 4 x 2 nodes; only tiles
 // holding fluid are launched, one block of 256 threads each, and a tile's
 // fluid nodes are compacted (fluid ids tile base + rank, x fastest inside the
-// tile).
+// tile except that the nodes of the three planes at each x end come first).
 #pragma once
 
 #include "lbm_device.hpp"
