@@ -329,9 +329,19 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB elementwise copy (reference for HBM byte counters)")
+    ap.add_argument("--adjoint-only", default=None, metavar="CASES",
+                    help="only time the named adjoint cases (comma list of adjoint64, adjoint64_trapped, "
+                         "adjoint128) and print their records, one JSON line each")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.adjoint_only:
+        wanted = [c for c in args.adjoint_only.split(",") if c]
+        for label, w_a, rho_a, region_a in adjoint_cases():
+            if label.split(":")[0] in wanted:
+                _log(f"timing the adjoint ({label.split(':')[0]}, 500 steps, checkpoint every 25)")
+                print(json.dumps(run_adjoint(label, w_a, rho_a, region_a)), flush=True)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

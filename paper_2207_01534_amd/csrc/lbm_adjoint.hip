@@ -19,13 +19,26 @@
 // dL/df_i(t) at a fluid node is lambda_loc_i + rhobar, kept as the two parts
 // and added where the next reverse step gathers them.  Both are indexed by
 // fluid id (plane stride np, like the populations), so their gathers touch
-// no solid slots; Abar and Nbar stay indexed by lattice node, since solid
-// neighbours read them.
+// no solid slots; lambda holds the two components of a direction side by
+// side (one 8-byte access per direction, as the populations do).  Abar and
+// Nbar stay indexed by lattice node, since solid neighbours read them.
 #include "lbm_adjoint.hpp"
 
 namespace mclbm {
 
 using CF = CodecF32;
+
+// Work item of this thread for kernels over a 1D range of n items launched
+// on an XCD-aware grid (xcd_grid(blocks of 256)): the hardware deals
+// consecutive blocks round-robin to the 8 XCDs, so block b takes chunk
+// (b mod 8) * per + b / 8 and each XCD walks a contiguous run of chunks,
+// whose neighbour gathers then share that XCD's L2.  Returns -1 past n.
+__device__ __forceinline__ int xcd_item(int n) {
+    const int per = gridDim.x >> 3;
+    const int chunk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int k = chunk * (int)blockDim.x + (int)threadIdx.x;
+    return k < n ? k : -1;
+}
 
 // ---------------------------------------------------------------------------
 // Loss L = (1/|R|) sum_{fluid x in R} rho1 / (rho1 + rho2), FP64 partials.
@@ -203,11 +216,9 @@ __global__ __launch_bounds__(256) void k_adj_seed_flux(Pops<CF> P, const int* __
     if (m & SELF_SOLID) return;
     const uint32_t kf = (uint32_t)fid[nb.idx];
     const size_t np = (size_t)g.np;
+    float2* lam2 = reinterpret_cast<float2*>(lam);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        lam[(size_t)i * np + kf] = l0 + DX[i] * lj;
-        lam[(size_t)(Q + i) * np + kf] = l1 + DX[i] * lj;
-    }
+    for (int i = 0; i < Q; ++i) lam2[(size_t)i * np + kf] = make_float2(l0 + DX[i] * lj, l1 + DX[i] * lj);
     {
         float2* ab = reinterpret_cast<float2*>(abar);
         ab[nb.idx] = make_float2(a1, a2);
@@ -235,7 +246,8 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const int* __restr
     if (m & SELF_SOLID) return;
     const uint32_t kf = (uint32_t)fid[nb.idx];
     const size_t np = (size_t)g.np;
-    for (int k = 0; k < 2 * Q; ++k) lam[(size_t)k * np + kf] = 0.0f;
+    float2* lam2 = reinterpret_cast<float2*>(lam);
+    for (int i = 0; i < Q; ++i) lam2[(size_t)i * np + kf] = make_float2(0.0f, 0.0f);
     float2 r = make_float2(0.f, 0.f);
     if (region[nb.idx] && loss[1] > 0) {
         float f[2][Q];
@@ -263,8 +275,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
                                                      const float2* __restrict__ rbar_next,
                                                      float* __restrict__ lam_cur, float* __restrict__ abar,
                                                      Geo g, Phys ph) {
-    const int kf = blockIdx.x * blockDim.x + threadIdx.x;
-    if (kf >= nfluid) return;
+    const int kf = xcd_item(nfluid);
+    if (kf < 0) return;
     const int idx = node_of[kf];
     const int x = idx % g.nx, y = (idx / g.nx) % g.ny, z = idx / (g.nx * g.ny);
     const Nb nb(x, y, z, g);
@@ -299,17 +311,20 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
     // lambda* = dL/df*: the adjoint of streaming gathers from downstream
     float ls[2][Q];
     {
+        const float2* ln = reinterpret_cast<const float2*>(lam_next);
         const float2 rb0 = rbar_next[kf];
-        ls[0][0] = lam_next[kf] + rb0.x;
-        ls[1][0] = lam_next[(size_t)Q * np + kf] + rb0.y;
+        const float2 l0 = ln[kf];
+        ls[0][0] = l0.x + rb0.x;
+        ls[1][0] = l0.y + rb0.y;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const bool wall = (m >> i) & 1u;
             const uint32_t at = wall ? (uint32_t)kf : (uint32_t)fid[nb.at(i, +1)];
             const int dir = wall ? opp(i) : i;
             const float2 rb = rbar_next[at];
-            ls[0][i] = lam_next[(size_t)dir * np + at] + rb.x;
-            ls[1][i] = lam_next[(size_t)(Q + dir) * np + at] + rb.y;
+            const float2 lv = ln[(size_t)dir * np + at];
+            ls[0][i] = lv.x + rb.x;
+            ls[1][i] = lv.y + rb.y;
         }
     }
 
@@ -380,13 +395,12 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
     }
     // local part of dL/df_i(t): direct term, momentum term, density term
     const float keep = 1.0f - om;
+    float2* lc = reinterpret_cast<float2*>(lam_cur);
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const float ej = DX[i] * Pbar[0] + DY[i] * Pbar[1] + DZ[i] * Pbar[2];
-            lam_cur[(size_t)(s * Q + i) * np + kf] = keep * ls[s][i] + ej + rb[s];
-        }
+    for (int i = 0; i < Q; ++i) {
+        const float ej = DX[i] * Pbar[0] + DY[i] * Pbar[1] + DZ[i] * Pbar[2];
+        lc[(size_t)i * np + kf] = make_float2(keep * ls[0][i] + ej + rb[0], keep * ls[1][i] + ej + rb[1]);
+    }
 }
 
 // psibar(y) = -sum_k w_k e_k . Abar(y + e_k), both components.
@@ -416,8 +430,8 @@ __global__ __launch_bounds__(256) void k_adj_ivsd(const int* __restrict__ list, 
                                                   const float2* __restrict__ psi, const float* __restrict__ abar,
                                                   Geo g, double* __restrict__ grad_acc,
                                                   float2* __restrict__ nbar) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= count) return;
+    const int k = xcd_item(count);
+    if (k < 0) return;
     const int idx = list[k];
     const int x = idx % g.nx;
     const int y = (idx / g.nx) % g.ny;
@@ -451,8 +465,8 @@ __global__ __launch_bounds__(256) void k_adj_rho(const int* __restrict__ node_of
                                                  const uint32_t* __restrict__ nbm, const float* __restrict__ abar,
                                                  const float2* __restrict__ nbar, Geo g,
                                                  float2* __restrict__ rbar) {
-    const int kf = blockIdx.x * blockDim.x + threadIdx.x;
-    if (kf >= nfluid) return;
+    const int kf = xcd_item(nfluid);
+    if (kf < 0) return;
     const int idx = node_of[kf];
     const Nb nb(idx % g.nx, (idx / g.nx) % g.ny, idx / (g.nx * g.ny), g);
     const uint32_t m = nbm[nb.idx];
@@ -548,7 +562,7 @@ void launch_adj_collide(const Pops<CF>& P, const int* fid, const int* node_of, i
                         const float2* psi, const float* lam_next, const float2* rbar_next, float* lam_cur,
                         float* abar, const Geo& g, const Phys& ph, int odd, hipStream_t s) {
     if (nfluid <= 0) return;
-    const dim3 grid((nfluid + 255) / 256);
+    const dim3 grid(xcd_grid((nfluid + 255) / 256));
     if (odd)
         hipLaunchKernelGGL(k_adj_collide<true>, grid, dim3(256), 0, s, P, fid, node_of, nfluid, nbm, psi, lam_next,
                            rbar_next, lam_cur, abar, g, ph);
@@ -560,15 +574,15 @@ void launch_adj_collide(const Pops<CF>& P, const int* fid, const int* node_of, i
 void launch_adj_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, const float2* psi,
                      const float* abar, const Geo& g, double* grad_acc, float2* nbar, hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_adj_ivsd, dim3((count + 255) / 256), dim3(256), 0, s, list, xil, count, nbm, psi, abar,
-                       g, grad_acc, nbar);
+    hipLaunchKernelGGL(k_adj_ivsd, dim3(xcd_grid((count + 255) / 256)), dim3(256), 0, s, list, xil, count, nbm, psi,
+                       abar, g, grad_acc, nbar);
 }
 
 void launch_adj_rho(const int* node_of, int nfluid, const uint32_t* nbm, const float* abar, const float2* nbar,
                     const Geo& g, float2* rbar, hipStream_t s) {
     if (nfluid <= 0) return;
-    hipLaunchKernelGGL(k_adj_rho, dim3((nfluid + 255) / 256), dim3(256), 0, s, node_of, nfluid, nbm, abar, nbar,
-                       g, rbar);
+    hipLaunchKernelGGL(k_adj_rho, dim3(xcd_grid((nfluid + 255) / 256)), dim3(256), 0, s, node_of, nfluid, nbm, abar,
+                       nbar, g, rbar);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {

@@ -604,7 +604,7 @@ mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, in
 struct AdjointWork {
     char* seg[2];   // two segment buffers of `every` state slots
     char* psi[2];   // and of `every` psi-hat fields (n float2 each)
-    float* lam[2];   // [2][19][np], by fluid id
+    float* lam[2];   // [19][np] component pairs, by fluid id
     float* abar;     // [3][n] pairs (component 1, component 2), by lattice node (read at solid neighbours)
     float2* rbar[2]; // [np], by fluid id
     float2* nbar;
