@@ -424,6 +424,8 @@ __device__ __forceinline__ float2 psi_adjoint(const float* __restrict__ abar, co
 // ---------------------------------------------------------------------------
 // A2: boundary solid nodes.  rho~^s = chi^s N^s / D with chi = 1 +- xi gives
 // dL/dxi = psibar^1 N^1/D - psibar^2 N^2/D and Nbar^s = psibar^s chi^s / D.
+// N^s/D is read back from the forward's psi-hat at y (rho~^s / chi^s) and D
+// follows from the neighbourhood word, so no neighbour densities are loaded.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_adj_ivsd(const int* __restrict__ list, const float* __restrict__ xil,
                                                   int count, const uint32_t* __restrict__ nbm,
@@ -438,24 +440,16 @@ __global__ __launch_bounds__(256) void k_adj_ivsd(const int* __restrict__ list, 
     const int z = idx / (g.nx * g.ny);
     const Nb nb(x, y, z, g);
     const uint32_t m = nbm[idx];
-    const float2 pb = psi_adjoint(abar, nb, (size_t)g.n);
-    // all neighbour loads issued together (psi is read-only here); solid
-    // neighbours are dropped by a select
-    float2 r[Q];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) r[i] = psi[nb.at(i, +1)];
-    float den = 0.f, n0 = 0.f, n1 = 0.f;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const bool fluid = !((m >> i) & 1u);
-        den += fluid ? weight(i) : 0.0f;
-        n0 += fluid ? weight(i) * r[i].x : 0.0f;
-        n1 += fluid ? weight(i) * r[i].y : 0.0f;
-    }
-    const float inv = 1.0f / den;
+    const float2 vd = psi[idx];
     const float v = xil[k];
-    grad_acc[k] += (double)(pb.x * n0 * inv) - (double)(pb.y * n1 * inv);
-    nbar[idx] = make_float2(pb.x * (1.0f + v) * inv, pb.y * (1.0f - v) * inv);
+    const float2 pb = psi_adjoint(abar, nb, (size_t)g.n);
+    float den = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) den += ((m >> i) & 1u) ? 0.0f : weight(i);
+    const float inv = 1.0f / den;  // den > 0: the list holds only nodes with a fluid neighbour
+    const float c0 = 1.0f + v, c1 = 1.0f - v;  // > 0: |xi| < 1 at listed nodes
+    grad_acc[k] += (double)(pb.x * (vd.x / c0)) - (double)(pb.y * (vd.y / c1));
+    nbar[idx] = make_float2(pb.x * c0 * inv, pb.y * c1 * inv);
 }
 
 // ---------------------------------------------------------------------------
