@@ -322,6 +322,68 @@ __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, in
 
 
 
+// Two halos of the same positions staged together (the codec's previous-level
+// field and this level's psi-hat in the F16/BF16 collide-stream): the loads of
+// both are issued before the first LDS write, so the block waits for one
+// round trip instead of two (each staging waits for all of its thread's loads
+// in flight, in issue order).
+template <class T, class SrcA, class SrcB>
+__device__ __forceinline__ void stage_halo2(T (*ta)[HY][HX], SrcA srca, T (*tb)[HY][HX], SrcB srcb, int x0, int y0,
+                                            int z0, const Geo& g, T fill) {
+    constexpr int NW = NT / 64;
+    constexpr int RPW = (HZ * HY + NW - 1) / NW;
+    static_assert(2 * RPW <= 64 && HX == 66, "halo row split");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    auto row_base = [&](int r, bool& ok) {
+        const int pl = r / HY, hy = r - pl * HY;
+        int gy = y0 + hy - 1, gz = z0 - 1 + pl;
+        gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+        gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
+        ok = gy < g.ny;
+        return (uint32_t)(g.nx * (gy + g.ny * gz));
+    };
+    int gx = x0 + lane - 1;
+    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+    const bool inx = gx < g.nx;
+    const bool has_tail = lane < 2 * RPW;
+    const int tp = lane >> 1;
+    int gxt = x0 + 63 + (lane & 1);
+    gxt = gxt >= g.nx ? gxt - g.nx : gxt;
+    T va[RPW], vb[RPW];
+    uint32_t rbt = 0;
+    bool okt = false;
+#pragma unroll
+    for (int p = 0; p < RPW; ++p) {
+        bool ok;
+        const int r = wave + NW * p;
+        const uint32_t rb = row_base(r < HZ * HY ? r : 0, ok);
+        ok = ok && r < HZ * HY;
+        va[p] = (ok && inx) ? srca(rb + (uint32_t)gx) : fill;
+        vb[p] = (ok && inx) ? srcb(rb + (uint32_t)gx) : fill;
+        rbt = tp == p ? rb : rbt;
+        okt = tp == p ? ok : okt;
+    }
+    T vta = fill, vtb = fill;
+    if (has_tail && okt && gxt < g.nx) {
+        vta = srca(rbt + (uint32_t)gxt);
+        vtb = srcb(rbt + (uint32_t)gxt);
+    }
+#pragma unroll
+    for (int p = 0; p < RPW; ++p) {
+        const int r = wave + NW * p;
+        if (r < HZ * HY) {
+            ta[r / HY][r % HY][lane] = va[p];
+            tb[r / HY][r % HY][lane] = vb[p];
+        }
+    }
+    const int rt = wave + NW * tp;
+    if (has_tail && rt < HZ * HY) {
+        ta[rt / HY][rt % HY][64 + (lane & 1)] = vta;
+        tb[rt / HY][rt % HY][64 + (lane & 1)] = vtb;
+    }
+}
+
 // Fluid ids of the staged halo around one tile node: fid of x + s e_i, -1
 // at solid nodes.
 struct HaloFid {
@@ -496,9 +558,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
     RawNode<C> r;
     HaloFid h;
     if (j0 < count) fetch(j0, r, h);
-    stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
     if constexpr (C::kRef)
-        stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
+        stage_halo2(psit, [&](uint32_t i) { return ld(psi, i); }, reft, [&](uint32_t i) { return ld(rprev, i); }, x0,
+                    y0, z0, g, make_float2(0.f, 0.f));
+    else
+        stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
     __syncthreads();
     if (j0 < count) finish(j0, r, h);
     for (int j = j0 + NT; j < count; j += NT) {
