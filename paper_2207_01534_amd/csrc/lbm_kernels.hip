@@ -265,123 +265,93 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* _
 // thread j handles the tile's fluid nodes j and j + 256 (when they exist).
 // ---------------------------------------------------------------------------
 
-// Stage values of planes z0-1 .. z0+2 over the tile plus a one-node halo
-// (HZ x HY rows of HX values).  Wave w copies rows w, w + 4, ...: lane l
+// Staging of planes z0-1 .. z0+2 over the tile plus a one-node halo (HZ x HY
+// rows of HX values) into LDS.  Wave w copies rows w, w + 4, ...: lane l
 // takes column l of each, and lanes 0 .. 2*RPW-1 take the two end columns
-// 64-65 of those rows.  All loads of a thread are issued before the first
-// LDS write, so they are in flight together (and with any loads the caller
-// issued before).  Coordinates wrap periodically once; a position one wrap
-// cannot bring inside the lattice (extents below the tile size) gets the
-// fill value.
+// 64-65 of those rows.  Coordinates wrap periodically once; a position one
+// wrap cannot bring inside the lattice (extents below the tile size) gets the
+// fill value.  HaloSlots holds this thread's share of the positions; gather()
+// issues the loads of one field, put() writes them to LDS, and every gather
+// of a thread comes before its first put, so all of its loads (and any the
+// caller issued before) are in flight together: each put waits for the
+// thread's loads in issue order.
+struct HaloSlots {
+    static constexpr int NW = NT / 64;
+    static constexpr int RPW = (HZ * HY + NW - 1) / NW;  // rows per wave (the last ones may run past HZ*HY)
+    static_assert(2 * RPW <= 64 && HX == 66, "halo row split");
+    int lane, wave, gx, gxt, tp;
+    bool inx, has_tail;
+    const Geo& g;
+    int x0, y0, z0;
+    __device__ __forceinline__ HaloSlots(int x0_, int y0_, int z0_, const Geo& g_) : g(g_), x0(x0_), y0(y0_), z0(z0_) {
+        lane = threadIdx.x & 63;
+        wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        gx = x0 + lane - 1;
+        gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+        inx = gx < g.nx;
+        has_tail = lane < 2 * RPW;
+        tp = lane >> 1;  // row slot of this lane's end-column value
+        gxt = x0 + 63 + (lane & 1);
+        gxt = gxt >= g.nx ? gxt - g.nx : gxt;
+    }
+    __device__ __forceinline__ uint32_t row_base(int r, bool& ok) const {
+        const int pl = r / HY, hy = r - pl * HY;
+        int gy = y0 + hy - 1, gz = z0 - 1 + pl;
+        gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+        gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
+        ok = gy < g.ny;
+        return (uint32_t)(g.nx * (gy + g.ny * gz));
+    }
+    template <class T, class Src>
+    __device__ __forceinline__ void gather(Src src, T fill, T (&v)[RPW], T& vt) const {
+        uint32_t rbt = 0;
+        bool okt = false;
+#pragma unroll
+        for (int p = 0; p < RPW; ++p) {
+            bool ok;
+            const int r = wave + NW * p;
+            const uint32_t rb = row_base(r < HZ * HY ? r : 0, ok);
+            ok = ok && r < HZ * HY;
+            v[p] = (ok && inx) ? src(rb + (uint32_t)gx) : fill;
+            rbt = tp == p ? rb : rbt;
+            okt = tp == p ? ok : okt;
+        }
+        vt = fill;
+        if (has_tail && okt && gxt < g.nx) vt = src(rbt + (uint32_t)gxt);
+    }
+    template <class T>
+    __device__ __forceinline__ void put(T (*tile)[HY][HX], const T (&v)[RPW], T vt) const {
+#pragma unroll
+        for (int p = 0; p < RPW; ++p) {
+            const int r = wave + NW * p;
+            if (r < HZ * HY) tile[r / HY][r % HY][lane] = v[p];
+        }
+        const int rt = wave + NW * tp;
+        if (has_tail && rt < HZ * HY) tile[rt / HY][rt % HY][64 + (lane & 1)] = vt;
+    }
+};
+
 template <class T, class Src>
 __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, int z0, const Geo& g, Src src,
                                            T fill) {
-    constexpr int NW = NT / 64;
-    constexpr int RPW = (HZ * HY + NW - 1) / NW;  // rows per wave (the last ones may run past HZ*HY)
-    static_assert(2 * RPW <= 64 && HX == 66, "halo row split");
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    auto row_base = [&](int r, bool& ok) {
-        const int pl = r / HY, hy = r - pl * HY;
-        int gy = y0 + hy - 1, gz = z0 - 1 + pl;
-        gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-        gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
-        ok = gy < g.ny;
-        return (uint32_t)(g.nx * (gy + g.ny * gz));
-    };
-    int gx = x0 + lane - 1;
-    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
-    const bool inx = gx < g.nx;
-    const bool has_tail = lane < 2 * RPW;
-    const int tp = lane >> 1;                         // row slot of this lane's end-column value
-    int gxt = x0 + 63 + (lane & 1);
-    gxt = gxt >= g.nx ? gxt - g.nx : gxt;
-    T v[RPW];
-    uint32_t rbt = 0;
-    bool okt = false;
-#pragma unroll
-    for (int p = 0; p < RPW; ++p) {
-        bool ok;
-        const int r = wave + NW * p;
-        const uint32_t rb = row_base(r < HZ * HY ? r : 0, ok);
-        ok = ok && r < HZ * HY;
-        v[p] = (ok && inx) ? src(rb + (uint32_t)gx) : fill;
-        rbt = tp == p ? rb : rbt;
-        okt = tp == p ? ok : okt;
-    }
-    T vt = fill;
-    if (has_tail && okt && gxt < g.nx) vt = src(rbt + (uint32_t)gxt);
-#pragma unroll
-    for (int p = 0; p < RPW; ++p) {
-        const int r = wave + NW * p;
-        if (r < HZ * HY) tile[r / HY][r % HY][lane] = v[p];
-    }
-    const int rt = wave + NW * tp;
-    if (has_tail && rt < HZ * HY) tile[rt / HY][rt % HY][64 + (lane & 1)] = vt;
+    const HaloSlots h(x0, y0, z0, g);
+    T v[HaloSlots::RPW], vt;
+    h.gather(src, fill, v, vt);
+    h.put(tile, v, vt);
 }
 
-
-
-// Two halos of the same positions staged together (the codec's previous-level
-// field and this level's psi-hat in the F16/BF16 collide-stream): the loads of
-// both are issued before the first LDS write, so the block waits for one
-// round trip instead of two (each staging waits for all of its thread's loads
-// in flight, in issue order).
+// Two fields of the same positions staged together (this level's psi-hat and
+// the codec's previous-level field in the F16/BF16 collide-stream): one wait
+// for both instead of one each.
 template <class T, class SrcA, class SrcB>
 __device__ __forceinline__ void stage_halo2(T (*ta)[HY][HX], SrcA srca, T (*tb)[HY][HX], SrcB srcb, int x0, int y0,
                                             int z0, const Geo& g, T fill) {
-    constexpr int NW = NT / 64;
-    constexpr int RPW = (HZ * HY + NW - 1) / NW;
-    static_assert(2 * RPW <= 64 && HX == 66, "halo row split");
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    auto row_base = [&](int r, bool& ok) {
-        const int pl = r / HY, hy = r - pl * HY;
-        int gy = y0 + hy - 1, gz = z0 - 1 + pl;
-        gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-        gz = gz < 0 ? gz + g.nz : (gz >= g.nz ? gz - g.nz : gz);
-        ok = gy < g.ny;
-        return (uint32_t)(g.nx * (gy + g.ny * gz));
-    };
-    int gx = x0 + lane - 1;
-    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
-    const bool inx = gx < g.nx;
-    const bool has_tail = lane < 2 * RPW;
-    const int tp = lane >> 1;
-    int gxt = x0 + 63 + (lane & 1);
-    gxt = gxt >= g.nx ? gxt - g.nx : gxt;
-    T va[RPW], vb[RPW];
-    uint32_t rbt = 0;
-    bool okt = false;
-#pragma unroll
-    for (int p = 0; p < RPW; ++p) {
-        bool ok;
-        const int r = wave + NW * p;
-        const uint32_t rb = row_base(r < HZ * HY ? r : 0, ok);
-        ok = ok && r < HZ * HY;
-        va[p] = (ok && inx) ? srca(rb + (uint32_t)gx) : fill;
-        vb[p] = (ok && inx) ? srcb(rb + (uint32_t)gx) : fill;
-        rbt = tp == p ? rb : rbt;
-        okt = tp == p ? ok : okt;
-    }
-    T vta = fill, vtb = fill;
-    if (has_tail && okt && gxt < g.nx) {
-        vta = srca(rbt + (uint32_t)gxt);
-        vtb = srcb(rbt + (uint32_t)gxt);
-    }
-#pragma unroll
-    for (int p = 0; p < RPW; ++p) {
-        const int r = wave + NW * p;
-        if (r < HZ * HY) {
-            ta[r / HY][r % HY][lane] = va[p];
-            tb[r / HY][r % HY][lane] = vb[p];
-        }
-    }
-    const int rt = wave + NW * tp;
-    if (has_tail && rt < HZ * HY) {
-        ta[rt / HY][rt % HY][64 + (lane & 1)] = vta;
-        tb[rt / HY][rt % HY][64 + (lane & 1)] = vtb;
-    }
+    const HaloSlots h(x0, y0, z0, g);
+    T va[HaloSlots::RPW], vb[HaloSlots::RPW], vta, vtb;
+    h.gather(srca, fill, va, vta);
+    h.gather(srcb, fill, vb, vtb);
+    h.put(ta, va, vta);
+    h.put(tb, vb, vtb);
 }
 
 // Fluid ids of the staged halo around one tile node: fid of x + s e_i, -1
