@@ -104,7 +104,7 @@ __device__ __forceinline__ int block_rank(bool flag, int* wave_off, int* count) 
 
 __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* __restrict__ xi,
                                  Geo g, const int* __restrict__ offsets, int* __restrict__ list,
-                                 float* __restrict__ xil) {
+                                 float* __restrict__ xil, uint32_t* __restrict__ nbl) {
     __shared__ int wave_off[TN / 64];
     int x0, y0, z0;
     tile_origin(blockIdx.x, g, x0, y0, z0);
@@ -117,6 +117,7 @@ __global__ void k_boundary_write(const uint32_t* __restrict__ nbm, const float* 
         const int at = offsets[blockIdx.x] + rank;
         list[at] = idx;
         xil[at] = xi[idx];
+        nbl[at] = nbm[idx];
     }
 }
 
@@ -387,14 +388,16 @@ void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const floa
         stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
         __syncthreads();
     }
-    auto fetch = [&](int j, RawNode<C>& r, TilePos& q) {
+    // the F16/BF16 decoders also need the node's neighbourhood word; it is
+    // requested with the populations, not after the wait for them
+    auto fetch = [&](int j, RawNode<C>& r, TilePos& q, uint32_t& m) {
         const uint32_t k = (uint32_t)(base + j);
         q = TilePos(S.loc[k]);
         load_raw<C, ODD, WIDE>(r, P, k, HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1}, g.np);
+        m = C::kRef ? ld(nbm, (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)))) : 0u;
     };
-    auto finish = [&](const RawNode<C>& r, const TilePos& q) {
+    auto finish = [&](const RawNode<C>& r, const TilePos& q, uint32_t m) {
         const uint32_t idx = (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)));
-        const uint32_t m = C::kRef ? ld(nbm, idx) : 0u;
         const int tx = q.lx + 1, ty = q.ly + 1, tz = q.lz + 1;
         float f[2][Q];
         if constexpr (C::kRef) {
@@ -408,15 +411,16 @@ void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const floa
     const int j0 = threadIdx.x;
     RawNode<C> r;
     TilePos q(0);
-    if (j0 < count) fetch(j0, r, q);
+    uint32_t m = 0u;
+    if (j0 < count) fetch(j0, r, q, m);
     if constexpr (C::kRef) {
         stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
         __syncthreads();
     }
-    if (j0 < count) finish(r, q);
+    if (j0 < count) finish(r, q, m);
     for (int j = j0 + NT; j < count; j += NT) {
-        fetch(j, r, q);
-        finish(r, q);
+        fetch(j, r, q, m);
+        finish(r, q, m);
     }
 }
 
@@ -424,17 +428,21 @@ void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const floa
 // K1b: IVSD virtual solid density at boundary solid nodes (Eqs. 14-15):
 // rho~^(s) = chi^(s) sum_i w_i rho^(s)(x+e_i) [fluid] / sum_i w_i [fluid],
 // chi^(1) = 1 + xi, chi^(2) = 1 - xi.
+// The node's neighbourhood word comes from the list-ordered copy nbl, so it
+// is requested together with the node's index instead of after it: the
+// neighbour loads, whose addresses depend on both, then wait for one round
+// trip instead of two.
 __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, const float* __restrict__ xil,
-                                              int count, const uint32_t* __restrict__ nbm,
+                                              int count, const uint32_t* __restrict__ nbl,
                                               float2* __restrict__ psi, Geo g) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count) return;
     const int idx = list[k];
+    const uint32_t m = nbl[k];
     const int x = idx % g.nx;
     const int y = (idx / g.nx) % g.ny;
     const int z = idx / (g.nx * g.ny);
     const Nb nb(x, y, z, g);
-    const uint32_t m = nbm[idx];
     // all 18 neighbour loads issued together: a solid neighbour reads the
     // node's own entry instead (a value only this thread writes, after the
     // loads) and its term is dropped by a select
@@ -488,16 +496,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
         __syncthreads();
     }
     __shared__ float2 reft[C::kRef ? HZ : 1][HY][HX];
-    auto fetch = [&](int j, RawNode<C>& r, HaloFid& h) {
+    // the F16/BF16 codecs also need the node's neighbourhood word; it is
+    // requested with the populations, not after the wait for them
+    auto fetch = [&](int j, RawNode<C>& r, HaloFid& h, uint32_t& m) {
         const uint32_t k = (uint32_t)(base + j);
         const TilePos q(S.loc[k]);
         h = HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1};
         load_raw<C, ODD, WIDE>(r, P, k, h, g.np);
+        m = C::kRef ? ld(nbm, (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)))) : 0u;
     };
-    auto finish = [&](int j, const RawNode<C>& r, const HaloFid& h) {
+    auto finish = [&](int j, const RawNode<C>& r, const HaloFid& h, uint32_t m) {
         const uint32_t k = (uint32_t)(base + j);
-        const uint32_t idx = (uint32_t)(x0 + h.tx - 1 + g.nx * (y0 + h.ty - 1 + g.ny * (z0 + h.tz - 1)));
-        const uint32_t m = C::kRef ? ld(nbm, idx) : 0u;
         float f[2][Q];
         if constexpr (C::kRef) {
             auto prev_rel = [&](int dx, int dy, int dz) { return reft[h.tz + dz][h.ty + dy][h.tx + dx]; };
@@ -527,17 +536,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
     const int j0 = threadIdx.x;
     RawNode<C> r;
     HaloFid h;
-    if (j0 < count) fetch(j0, r, h);
+    uint32_t m = 0u;
+    if (j0 < count) fetch(j0, r, h, m);
     if constexpr (C::kRef)
         stage_halo2(psit, [&](uint32_t i) { return ld(psi, i); }, reft, [&](uint32_t i) { return ld(rprev, i); }, x0,
                     y0, z0, g, make_float2(0.f, 0.f));
     else
         stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
     __syncthreads();
-    if (j0 < count) finish(j0, r, h);
+    if (j0 < count) finish(j0, r, h, m);
     for (int j = j0 + NT; j < count; j += NT) {
-        fetch(j, r, h);
-        finish(j, r, h);
+        fetch(j, r, h, m);
+        finish(j, r, h, m);
     }
 }
 
@@ -679,12 +689,12 @@ void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hi
 int boundary_blocks(const Geo& g) { return tile_count(g); }
 
 void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int* total, int* list,
-                          float* xil, const Geo& g, hipStream_t s) {
+                          float* xil, uint32_t* nbl, const Geo& g, hipStream_t s) {
     const int nb = boundary_blocks(g);
     hipLaunchKernelGGL(k_boundary_count, dim3(nb), dim3(TX, TY, TZ), 0, s, nbm, g, counts);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, nb, total);
     hipLaunchKernelGGL(k_boundary_write, dim3(nb), dim3(TX, TY, TZ), 0, s, nbm, xi, g,
-                       (const int*)counts, list, xil);
+                       (const int*)counts, list, xil, nbl);
 }
 
 void launch_geometry_check(const uint32_t* nbm, const float* xi, const Geo& g, unsigned long long* out,
@@ -711,9 +721,10 @@ void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const in
 
 template <class C>
 void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,
-                 const int* list, const float* xil, int nbound, const Geo& g, float G, hipStream_t s) {
+                 const int* list, const float* xil, const uint32_t* nbl, int nbound, const Geo& g, float G,
+                 hipStream_t s) {
     hipLaunchKernelGGL(k_init_ref, row_grid(g), dim3(64), 0, s, nbm, rho, rprev, g);
-    launch_ivsd(list, xil, nbound, nbm, rprev, g, s);
+    launch_ivsd(list, xil, nbl, nbound, rprev, g, s);
     hipLaunchKernelGGL(k_init<C>, row_grid(g), dim3(64), 0, s, P, nbm, fid, (const float2*)rprev, g, G);
 }
 
@@ -737,11 +748,10 @@ void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, cons
              : launch_density_as<C, false, false>(P, S, nbm, rprev, psi, g, G, s);
 }
 
-void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
-                 const Geo& g, hipStream_t s) {
+void launch_ivsd(const int* list, const float* xil, const uint32_t* nbl, int count, float2* psi, const Geo& g,
+                 hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_ivsd, dim3((count + 255) / 256), dim3(256), 0, s, list, xil, count, nbm, psi,
-                       g);
+    hipLaunchKernelGGL(k_ivsd, dim3((count + 255) / 256), dim3(256), 0, s, list, xil, count, nbl, psi, g);
 }
 
 template <class C, bool ODD, bool WIDE>
@@ -812,7 +822,8 @@ hipError_t scratch_address(int device, double** out) {
 
 #define MCLBM_INSTANTIATE(C)                                                                              \
     template void launch_init<C>(const Pops<C>&, const uint32_t*, const int*, const float*, float2*,      \
-                                 const int*, const float*, int, const Geo&, float, hipStream_t);          \
+                                 const int*, const float*, const uint32_t*, int, const Geo&, float,      \
+                                 hipStream_t);                                                          \
     template void launch_density<C>(const Pops<C>&, const Sparse&, const uint32_t*, const float2*,        \
                                     float2*, const Geo&, float, int, hipStream_t);                        \
     template void launch_collide_stream<C>(const Pops<C>&, const Pops<C>&, const Sparse&, const uint32_t*, \

@@ -18,8 +18,10 @@ struct Sparse {
 void launch_store_words(uint64_t* dst, const uint64_t (&w)[4], hipStream_t s);
 void launch_neighbour_bits(const uint8_t* solid, uint32_t* nbm, const Geo& g, hipStream_t s);
 int boundary_blocks(const Geo& g);
+// Boundary solids (solid nodes with a fluid neighbour) in tile order: their
+// lattice indices (list), adhesion values (xil) and neighbourhood words (nbl).
 void launch_boundary_list(const uint32_t* nbm, const float* xi, int* counts, int* total, int* list,
-                          float* xil, const Geo& g, hipStream_t s);
+                          float* xil, uint32_t* nbl, const Geo& g, hipStream_t s);
 // Checks a candidate geometry (neighbour words nbm, adhesion xi) without
 // changing anything else: out[0] <- boundary solids with |xi| not < 1,
 // out[1] <- fluid nodes, out[2] <- order-independent fingerprint of the
@@ -43,12 +45,13 @@ void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const in
 // values are taken.  G: the cohesion parameter (codec predictors).
 template <class C>
 void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const float* rho, float2* rprev,
-                 const int* list, const float* xil, int nbound, const Geo& g, float G, hipStream_t s);
+                 const int* list, const float* xil, const uint32_t* nbl, int nbound, const Geo& g, float G,
+                 hipStream_t s);
 template <class C>
 void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
                     const Geo& g, float G, int odd, hipStream_t s);
-void launch_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, float2* psi,
-                 const Geo& g, hipStream_t s);
+void launch_ivsd(const int* list, const float* xil, const uint32_t* nbl, int count, float2* psi, const Geo& g,
+                 hipStream_t s);
 template <class C>
 void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
                            const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, int odd,

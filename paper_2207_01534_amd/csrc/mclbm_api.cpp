@@ -38,7 +38,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t elem_bytes(int storage) { return storage == MCLBM_F32 ? 4 : 2; }
 
 struct Layout {
-    size_t mv, rest, R0, R1, nbm, list, xil, counts, partial, misc, total;
+    size_t mv, rest, R0, R1, nbm, list, xil, nbl, counts, partial, misc, total;
     size_t fid, loc, tcnt, tbase, tapos, tact, held;
     size_t mv_bytes, rest_bytes, r_bytes;
     int np, cap;
@@ -75,6 +75,7 @@ Layout make_layout(const mclbm_params& p) {
     L.nbm = take(n * sizeof(uint32_t));
     L.list = take(n * sizeof(int));
     L.xil = take(n * sizeof(float));
+    L.nbl = take(n * sizeof(uint32_t));
     L.counts = take((size_t)boundary_blocks(g) * sizeof(int));
     L.partial = take((size_t)fields_blocks(g) * 8 * sizeof(double));
     L.fid = take(n * sizeof(int));
@@ -150,6 +151,7 @@ struct mclbm_lattice {
     uint32_t* nbm() const { return (uint32_t*)(ws + L.nbm); }
     int* list() const { return (int*)(ws + L.list); }
     float* xil() const { return (float*)(ws + L.xil); }
+    uint32_t* nbl() const { return (uint32_t*)(ws + L.nbl); }
     double* partial() const { return (double*)(ws + L.partial); }
     int* misc_int() const { return (int*)(ws + L.misc); }
     double* diag_out() const { return (double*)(ws + L.misc + 64); }     // 8 doubles
@@ -185,7 +187,7 @@ struct mclbm_lattice {
             using C = decltype(c);
             launch_density<C>(pops<C>(), sparse(), nbm(), rprev, psi, g, ph.G, odd, stream);
         });
-        launch_ivsd(list(), xil(), nbound, nbm(), psi, g, stream);
+        launch_ivsd(list(), xil(), nbl(), nbound, psi, g, stream);
         if (open) launch_open_mirror(psi, g, stream);
     }
     void fields(float* o_rho, float* o_u, float* o_F, float* o_P, double* partial, double* out,
@@ -278,7 +280,7 @@ mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, cons
     lat->generation += 1;
     HIP_TRY(hipMemcpyAsync(lat->nbm(), cand, (size_t)g.n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     int* counts = (int*)(lat->ws + L.counts);
-    launch_boundary_list(lat->nbm(), d_xi, counts, lat->misc_int(), lat->list(), lat->xil(), g, s);
+    launch_boundary_list(lat->nbm(), d_xi, counts, lat->misc_int(), lat->list(), lat->xil(), lat->nbl(), g, s);
     int* tcnt = (int*)(lat->ws + L.tcnt);
     int* tbase = (int*)(lat->ws + L.tbase);
     int* tapos = (int*)(lat->ws + L.tapos);
@@ -318,8 +320,8 @@ mclbm_status mclbm_init_equilibrium(mclbm_lattice* lat, const float* d_rho) {
     // state at t = 0; the codecs' reference density of the previous level is R[1]
     lat->with_codec([&](auto c) {
         using C = decltype(c);
-        launch_init<C>(lat->pops<C>(), lat->nbm(), lat->fid(), d_rho, lat->R(1), lat->list(), lat->xil(), lat->nbound,
-                       lat->g, lat->ph.G, lat->stream);
+        launch_init<C>(lat->pops<C>(), lat->nbm(), lat->fid(), d_rho, lat->R(1), lat->list(), lat->xil(), lat->nbl(),
+                       lat->nbound, lat->g, lat->ph.G, lat->stream);
     });
     HIP_TRY(hipGetLastError());
     lat->t = 0;
@@ -354,7 +356,7 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
                               lat->stream);
             mark(0);
             mark(1);
-            launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, lat->g, lat->stream);
+            launch_ivsd(lat->list(), lat->xil(), lat->nbl(), lat->nbound, psi, lat->g, lat->stream);
             mark(1);
             if (lat->open) launch_open_mirror(psi, lat->g, lat->stream);
             mark(2);
@@ -785,7 +787,7 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
             float2* psi = (float2*)(W.psi[b] + (size_t)k * psi_stride);
             launch_density<CodecF32>(sk, lat->sparse(), lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g,
                                      lat->ph.G, odd, s2);
-            launch_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, g, s2);
+            launch_ivsd(lat->list(), lat->xil(), lat->nbl(), lat->nbound, psi, g, s2);
             if (k + 1 < len) {
                 const Pops<CodecF32> sn = slot_pops(W.seg[b] + (size_t)(k + 1) * slot, L);
                 launch_collide_stream<CodecF32>(sk, sn, lat->sparse(), lat->nbm(), psi, psi, g, lat->ph, odd, s2);
