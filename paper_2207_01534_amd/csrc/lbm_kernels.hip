@@ -185,7 +185,8 @@ __global__ void k_tile_count(const uint32_t* __restrict__ nbm, Geo g, int* __res
 // other, instead of one short run per row.
 __global__ void k_tile_ids(const uint32_t* __restrict__ nbm, Geo g, const int* __restrict__ base,
                            const int* __restrict__ cnt, const int* __restrict__ active_pos,
-                           int* __restrict__ fid, uint16_t* __restrict__ loc, int* __restrict__ active) {
+                           int* __restrict__ fid, uint16_t* __restrict__ loc, uint32_t* __restrict__ nbf,
+                           int* __restrict__ active) {
     __shared__ int wave_off[TN / 64];
     int x0, y0, z0;
     tile_origin(blockIdx.x, g, x0, y0, z0);
@@ -200,7 +201,10 @@ __global__ void k_tile_ids(const uint32_t* __restrict__ nbm, Geo g, const int* _
     const int rank_rest = block_rank(fluid && !edge, wave_off, &c);
     const int rank = edge ? rank_edge : c_edge + rank_rest;
     if (inside) fid[idx] = fluid ? base[blockIdx.x] + rank : -1;
-    if (fluid) loc[base[blockIdx.x] + rank] = (uint16_t)(threadIdx.x + TX * (threadIdx.y + TY * threadIdx.z));
+    if (fluid) {
+        loc[base[blockIdx.x] + rank] = (uint16_t)(threadIdx.x + TX * (threadIdx.y + TY * threadIdx.z));
+        nbf[base[blockIdx.x] + rank] = nbm[idx];
+    }
     if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0 && cnt[blockIdx.x] > 0)
         active[active_pos[blockIdx.x]] = blockIdx.x;
 }
@@ -374,8 +378,7 @@ struct HaloFid {
 // hold ~105 VGPRs.
 template <class C, bool ODD, bool WIDE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 6 : (C::kRef ? 7 : 8))))
-void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const float2* __restrict__ rprev,
-               float2* __restrict__ psi, Geo g, float G) {
+void k_density(Pops<C> P, Sparse S, const float2* __restrict__ rprev, float2* __restrict__ psi, Geo g, float G) {
     const int a = active_of_block(S.nactive);
     if (a < 0) return;
     const int t = S.active[a];
@@ -384,17 +387,24 @@ void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const floa
     const int base = S.base[t], count = S.count[t];
     __shared__ int fidt[ODD ? HZ : 1][HY][HX];
     __shared__ float2 reft[C::kRef ? HZ : 1][HY][HX];
+    // with the F16/BF16 codecs the first node's in-tile position is requested
+    // before the fluid-id halo is staged, so that the odd level's gathers wait
+    // for one round trip after the halo, not two (measured neutral to slightly
+    // slower for FP32, whose kernels load it in fetch)
+    const int j0 = threadIdx.x;
+    const uint16_t loc0 = (C::kRef && j0 < count) ? S.loc[base + j0] : (uint16_t)0;
     if constexpr (ODD) {
         stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
         __syncthreads();
     }
-    // the F16/BF16 decoders also need the node's neighbourhood word; it is
-    // requested with the populations, not after the wait for them
-    auto fetch = [&](int j, RawNode<C>& r, TilePos& q, uint32_t& m) {
+    // the F16/BF16 decoders also need the node's neighbourhood word (by fluid
+    // id, so coalesced and with no lookup before it); it is requested with the
+    // populations, not after the wait for them
+    auto fetch = [&](int j, uint16_t lc, RawNode<C>& r, TilePos& q, uint32_t& m) {
         const uint32_t k = (uint32_t)(base + j);
-        q = TilePos(S.loc[k]);
+        q = TilePos(C::kRef ? lc : S.loc[k]);
         load_raw<C, ODD, WIDE>(r, P, k, HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1}, g.np);
-        m = C::kRef ? ld(nbm, (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)))) : 0u;
+        m = C::kRef ? S.nbf[k] : 0u;
     };
     auto finish = [&](const RawNode<C>& r, const TilePos& q, uint32_t m) {
         const uint32_t idx = (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)));
@@ -408,18 +418,17 @@ void k_density(Pops<C> P, Sparse S, const uint32_t* __restrict__ nbm, const floa
         }
         st(psi, idx, make_float2(sum19(f[0]), sum19(f[1])));
     };
-    const int j0 = threadIdx.x;
     RawNode<C> r;
     TilePos q(0);
     uint32_t m = 0u;
-    if (j0 < count) fetch(j0, r, q, m);
+    if (j0 < count) fetch(j0, loc0, r, q, m);
     if constexpr (C::kRef) {
         stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
         __syncthreads();
     }
     if (j0 < count) finish(r, q, m);
     for (int j = j0 + NT; j < count; j += NT) {
-        fetch(j, r, q, m);
+        fetch(j, C::kRef ? S.loc[base + j] : (uint16_t)0, r, q, m);
         finish(r, q, m);
     }
 }
@@ -480,7 +489,6 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
 // less than the lost wave).
 template <class C, bool ODD, bool WIDE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 : 4))) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
-                                                       const uint32_t* __restrict__ nbm,
                                                        const float2* __restrict__ rprev,
                                                        const float2* __restrict__ psi, Geo g, Phys ph) {
     const int a = active_of_block(S.nactive);
@@ -491,19 +499,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
     const int base = S.base[t], count = S.count[t];
     __shared__ float2 psit[HZ][HY][HX];
     __shared__ int fidt[ODD ? HZ : 1][HY][HX];
+    // with the F16/BF16 codecs the first node's in-tile position is requested
+    // before the fluid-id halo is staged, so that the odd level's gathers wait
+    // for one round trip after the halo, not two (measured neutral to slightly
+    // slower for FP32, whose kernels load it in fetch)
+    const int j0 = threadIdx.x;
+    const uint16_t loc0 = (C::kRef && j0 < count) ? S.loc[base + j0] : (uint16_t)0;
     if constexpr (ODD) {
         stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
         __syncthreads();
     }
     __shared__ float2 reft[C::kRef ? HZ : 1][HY][HX];
-    // the F16/BF16 codecs also need the node's neighbourhood word; it is
-    // requested with the populations, not after the wait for them
-    auto fetch = [&](int j, RawNode<C>& r, HaloFid& h, uint32_t& m) {
+    // the F16/BF16 codecs also need the node's neighbourhood word (by fluid
+    // id, so coalesced and with no lookup before it); it is requested with the
+    // populations, not after the wait for them
+    auto fetch = [&](int j, uint16_t lc, RawNode<C>& r, HaloFid& h, uint32_t& m) {
         const uint32_t k = (uint32_t)(base + j);
-        const TilePos q(S.loc[k]);
+        const TilePos q(C::kRef ? lc : S.loc[k]);
         h = HaloFid{fidt, q.lx + 1, q.ly + 1, q.lz + 1};
         load_raw<C, ODD, WIDE>(r, P, k, h, g.np);
-        m = C::kRef ? ld(nbm, (uint32_t)(x0 + q.lx + g.nx * (y0 + q.ly + g.ny * (z0 + q.lz)))) : 0u;
+        m = C::kRef ? S.nbf[k] : 0u;
     };
     auto finish = [&](int j, const RawNode<C>& r, const HaloFid& h, uint32_t m) {
         const uint32_t k = (uint32_t)(base + j);
@@ -533,11 +548,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
             f, D, rho, [&](int i) { return pred_write(i, (bool)((m >> i) & 1u), cur_rel, ph.G); },
             own.x + own.y, C::kRef ? inv_total(own) : 0.0f, k, h, g.np);
     };
-    const int j0 = threadIdx.x;
     RawNode<C> r;
     HaloFid h;
     uint32_t m = 0u;
-    if (j0 < count) fetch(j0, r, h, m);
+    if (j0 < count) fetch(j0, loc0, r, h, m);
     if constexpr (C::kRef)
         stage_halo2(psit, [&](uint32_t i) { return ld(psi, i); }, reft, [&](uint32_t i) { return ld(rprev, i); }, x0,
                     y0, z0, g, make_float2(0.f, 0.f));
@@ -546,7 +560,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
     __syncthreads();
     if (j0 < count) finish(j0, r, h, m);
     for (int j = j0 + NT; j < count; j += NT) {
-        fetch(j, r, h, m);
+        fetch(j, C::kRef ? S.loc[base + j] : (uint16_t)0, r, h, m);
         finish(j, r, h, m);
     }
 }
@@ -713,9 +727,9 @@ void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, 
 }
 
 void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const int* base, const int* apos, int* fid,
-                     uint16_t* loc, int* active, hipStream_t s) {
+                     uint16_t* loc, uint32_t* nbf, int* active, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_ids, dim3(tile_count(g)), dim3(TX, TY, TZ), 0, s, nbm, g, base, cnt, apos, fid, loc,
-                       active);
+                       nbf, active);
 }
 
 
@@ -729,23 +743,22 @@ void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const fl
 }
 
 template <class C, bool ODD, bool WIDE>
-static void launch_density_as(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev,
-                              float2* psi, const Geo& g, float G, hipStream_t s) {
-    hipLaunchKernelGGL((k_density<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, nbm, rprev, psi,
-                       g, G);
+static void launch_density_as(const Pops<C>& P, const Sparse& S, const float2* rprev, float2* psi, const Geo& g,
+                              float G, hipStream_t s) {
+    hipLaunchKernelGGL((k_density<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, rprev, psi, g, G);
 }
 
 template <class C>
-void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
-                    const Geo& g, float G, int odd, hipStream_t s) {
+void launch_density(const Pops<C>& P, const Sparse& S, const float2* rprev, float2* psi, const Geo& g, float G,
+                    int odd, hipStream_t s) {
     if (S.nactive <= 0) return;
     const bool wide = pops_wide(g.np);
     if (odd)
-        wide ? launch_density_as<C, true, true>(P, S, nbm, rprev, psi, g, G, s)
-             : launch_density_as<C, true, false>(P, S, nbm, rprev, psi, g, G, s);
+        wide ? launch_density_as<C, true, true>(P, S, rprev, psi, g, G, s)
+             : launch_density_as<C, true, false>(P, S, rprev, psi, g, G, s);
     else
-        wide ? launch_density_as<C, false, true>(P, S, nbm, rprev, psi, g, G, s)
-             : launch_density_as<C, false, false>(P, S, nbm, rprev, psi, g, G, s);
+        wide ? launch_density_as<C, false, true>(P, S, rprev, psi, g, G, s)
+             : launch_density_as<C, false, false>(P, S, rprev, psi, g, G, s);
 }
 
 void launch_ivsd(const int* list, const float* xil, const uint32_t* nbl, int count, float2* psi, const Geo& g,
@@ -755,24 +768,23 @@ void launch_ivsd(const int* list, const float* xil, const uint32_t* nbl, int cou
 }
 
 template <class C, bool ODD, bool WIDE>
-static void launch_collide_as(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
-                              const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, hipStream_t s) {
-    hipLaunchKernelGGL((k_collide_stream<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, nbm,
-                       rprev, psi, g, ph);
+static void launch_collide_as(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const float2* rprev,
+                              const float2* psi, const Geo& g, const Phys& ph, hipStream_t s) {
+    hipLaunchKernelGGL((k_collide_stream<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, rprev,
+                       psi, g, ph);
 }
 
 template <class C>
-void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
-                           const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, int odd,
-                           hipStream_t s) {
+void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const float2* rprev,
+                           const float2* psi, const Geo& g, const Phys& ph, int odd, hipStream_t s) {
     if (S.nactive <= 0) return;
     const bool wide = pops_wide(g.np);
     if (odd)
-        wide ? launch_collide_as<C, true, true>(P, D, S, nbm, rprev, psi, g, ph, s)
-             : launch_collide_as<C, true, false>(P, D, S, nbm, rprev, psi, g, ph, s);
+        wide ? launch_collide_as<C, true, true>(P, D, S, rprev, psi, g, ph, s)
+             : launch_collide_as<C, true, false>(P, D, S, rprev, psi, g, ph, s);
     else
-        wide ? launch_collide_as<C, false, true>(P, D, S, nbm, rprev, psi, g, ph, s)
-             : launch_collide_as<C, false, false>(P, D, S, nbm, rprev, psi, g, ph, s);
+        wide ? launch_collide_as<C, false, true>(P, D, S, rprev, psi, g, ph, s)
+             : launch_collide_as<C, false, false>(P, D, S, rprev, psi, g, ph, s);
 }
 
 int fields_blocks(const Geo& g) {
@@ -824,11 +836,10 @@ hipError_t scratch_address(int device, double** out) {
     template void launch_init<C>(const Pops<C>&, const uint32_t*, const int*, const float*, float2*,      \
                                  const int*, const float*, const uint32_t*, int, const Geo&, float,      \
                                  hipStream_t);                                                          \
-    template void launch_density<C>(const Pops<C>&, const Sparse&, const uint32_t*, const float2*,        \
-                                    float2*, const Geo&, float, int, hipStream_t);                        \
-    template void launch_collide_stream<C>(const Pops<C>&, const Pops<C>&, const Sparse&, const uint32_t*, \
-                                           const float2*, const float2*, const Geo&, const Phys&, int,    \
-                                           hipStream_t);                                                  \
+    template void launch_density<C>(const Pops<C>&, const Sparse&, const float2*, float2*, const Geo&,    \
+                                    float, int, hipStream_t);                                             \
+    template void launch_collide_stream<C>(const Pops<C>&, const Pops<C>&, const Sparse&, const float2*,   \
+                                           const float2*, const Geo&, const Phys&, int, hipStream_t);    \
     template void launch_fields<C>(const Pops<C>&, const int*, const uint32_t*, const float2*,            \
                                    const float2*, const Geo&, const Phys&, int, float*, float*, float*,   \
                                    float*, double*, double*, int, hipStream_t, int);

@@ -11,6 +11,7 @@ struct Sparse {
     const int* base;     // per tile: fluid id of its first fluid node
     const int* count;    // per tile: number of fluid nodes
     const uint16_t* loc; // per fluid node: position inside its tile (x + 64 (y + 4 z))
+    const uint32_t* nbf; // per fluid node: its neighbourhood word (the F16/BF16 codecs' wall bits)
     const int* fid;      // per lattice node: fluid id, -1 at solid
     int nactive;
 };
@@ -33,10 +34,10 @@ int tile_count(const Geo& g);
 // totals[1] <- number of tiles holding fluid.
 void launch_tile_census(const uint32_t* nbm, const Geo& g, int* cnt, int* base, int* apos, int* totals,
                         hipStream_t s);
-// Fluid ids, in-tile positions and the active tile list; loc must hold
-// totals[0] entries.
+// Fluid ids, in-tile positions, neighbourhood words by fluid id and the
+// active tile list; loc and nbf must hold totals[0] entries.
 void launch_tile_ids(const uint32_t* nbm, const Geo& g, const int* cnt, const int* base, const int* apos, int* fid,
-                     uint16_t* loc, int* active, hipStream_t s);
+                     uint16_t* loc, uint32_t* nbf, int* active, hipStream_t s);
 
 // Initial state from the densities rho [2][n].  rprev receives the
 // pseudopotential field of the level before the first (the initial densities
@@ -48,14 +49,13 @@ void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const fl
                  const int* list, const float* xil, const uint32_t* nbl, int nbound, const Geo& g, float G,
                  hipStream_t s);
 template <class C>
-void launch_density(const Pops<C>& P, const Sparse& S, const uint32_t* nbm, const float2* rprev, float2* psi,
-                    const Geo& g, float G, int odd, hipStream_t s);
+void launch_density(const Pops<C>& P, const Sparse& S, const float2* rprev, float2* psi, const Geo& g, float G,
+                    int odd, hipStream_t s);
 void launch_ivsd(const int* list, const float* xil, const uint32_t* nbl, int count, float2* psi, const Geo& g,
                  hipStream_t s);
 template <class C>
-void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const uint32_t* nbm,
-                           const float2* rprev, const float2* psi, const Geo& g, const Phys& ph, int odd,
-                           hipStream_t s);
+void launch_collide_stream(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const float2* rprev,
+                           const float2* psi, const Geo& g, const Phys& ph, int odd, hipStream_t s);
 int fields_blocks(const Geo& g);
 // Readouts and the diagnostics reduction.  max_blocks > 0 caps the grid (each
 // block then sums several 64 x 4 patches), which bounds the partials to

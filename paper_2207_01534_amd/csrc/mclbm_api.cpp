@@ -39,7 +39,7 @@ size_t elem_bytes(int storage) { return storage == MCLBM_F32 ? 4 : 2; }
 
 struct Layout {
     size_t mv, rest, R0, R1, nbm, list, xil, nbl, counts, partial, misc, total;
-    size_t fid, loc, tcnt, tbase, tapos, tact, held;
+    size_t fid, loc, nbf, tcnt, tbase, tapos, tact, held;
     size_t mv_bytes, rest_bytes, r_bytes;
     int np, cap;
 };
@@ -80,6 +80,7 @@ Layout make_layout(const mclbm_params& p) {
     L.partial = take((size_t)fields_blocks(g) * 8 * sizeof(double));
     L.fid = take(n * sizeof(int));
     L.loc = take((size_t)L.cap * sizeof(uint16_t));
+    L.nbf = take((size_t)L.cap * sizeof(uint32_t));
     L.tcnt = take(nt * sizeof(int));
     L.tbase = take(nt * sizeof(int));
     L.tapos = take(nt * sizeof(int));
@@ -162,7 +163,7 @@ struct mclbm_lattice {
     int* fid() const { return (int*)(ws + L.fid); }
     Sparse sparse() const {
         return Sparse{(const int*)(ws + L.tact), (const int*)(ws + L.tbase), (const int*)(ws + L.tcnt),
-                      (const uint16_t*)(ws + L.loc), fid(), nactive};
+                      (const uint16_t*)(ws + L.loc), (const uint32_t*)(ws + L.nbf), fid(), nactive};
     }
 
     template <class C>
@@ -185,7 +186,7 @@ struct mclbm_lattice {
         const float2* rprev = R((int)((t + 1) & 1));
         with_codec([&](auto c) {
             using C = decltype(c);
-            launch_density<C>(pops<C>(), sparse(), nbm(), rprev, psi, g, ph.G, odd, stream);
+            launch_density<C>(pops<C>(), sparse(), rprev, psi, g, ph.G, odd, stream);
         });
         launch_ivsd(list(), xil(), nbl(), nbound, psi, g, stream);
         if (open) launch_open_mirror(psi, g, stream);
@@ -286,7 +287,7 @@ mclbm_status mclbm_set_geometry(mclbm_lattice* lat, const uint8_t* d_solid, cons
     int* tapos = (int*)(lat->ws + L.tapos);
     launch_tile_census(lat->nbm(), g, tcnt, tbase, tapos, lat->misc_int() + 1, s);
     launch_tile_ids(lat->nbm(), g, tcnt, tbase, tapos, lat->fid(), (uint16_t*)(lat->ws + L.loc),
-                    (int*)(lat->ws + L.tact), s);
+                    (uint32_t*)(lat->ws + L.nbf), (int*)(lat->ws + L.tact), s);
     HIP_TRY(hipGetLastError());
     int totals[3] = {0, 0, 0};  // boundary solids, fluid nodes, active tiles
     HIP_TRY(hipMemcpyAsync(totals, lat->misc_int(), sizeof(totals), hipMemcpyDeviceToHost, s));
@@ -352,16 +353,15 @@ mclbm_status mclbm_step(mclbm_lattice* lat, int32_t nsteps) {
         lat->with_codec([&](auto c) {
             using C = decltype(c);
             mark(0);
-            launch_density<C>(lat->pops<C>(), lat->sparse(), lat->nbm(), rprev, psi, lat->g, lat->ph.G, odd,
-                              lat->stream);
+            launch_density<C>(lat->pops<C>(), lat->sparse(), rprev, psi, lat->g, lat->ph.G, odd, lat->stream);
             mark(0);
             mark(1);
             launch_ivsd(lat->list(), lat->xil(), lat->nbl(), lat->nbound, psi, lat->g, lat->stream);
             mark(1);
             if (lat->open) launch_open_mirror(psi, lat->g, lat->stream);
             mark(2);
-            launch_collide_stream<C>(lat->pops<C>(), lat->pops<C>(), lat->sparse(), lat->nbm(), rprev, psi, lat->g,
-                                     lat->ph, odd, lat->stream);
+            launch_collide_stream<C>(lat->pops<C>(), lat->pops<C>(), lat->sparse(), rprev, psi, lat->g, lat->ph, odd,
+                                     lat->stream);
             mark(2);
             if (lat->open)
                 launch_open_rebuild<C>(lat->pops<C>(), lat->fid(), psi, lat->held(), lat->g, 1 - odd,
@@ -785,12 +785,12 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
             const int odd = (int)((ta + k) & 1);
             const Pops<CodecF32> sk = slot_pops(W.seg[b] + (size_t)k * slot, L);
             float2* psi = (float2*)(W.psi[b] + (size_t)k * psi_stride);
-            launch_density<CodecF32>(sk, lat->sparse(), lat->nbm(), lat->R(0) /* not read for FP32 */, psi, g,
-                                     lat->ph.G, odd, s2);
+            launch_density<CodecF32>(sk, lat->sparse(), lat->R(0) /* not read for FP32 */, psi, g, lat->ph.G, odd,
+                                     s2);
             launch_ivsd(lat->list(), lat->xil(), lat->nbl(), lat->nbound, psi, g, s2);
             if (k + 1 < len) {
                 const Pops<CodecF32> sn = slot_pops(W.seg[b] + (size_t)(k + 1) * slot, L);
-                launch_collide_stream<CodecF32>(sk, sn, lat->sparse(), lat->nbm(), psi, psi, g, lat->ph, odd, s2);
+                launch_collide_stream<CodecF32>(sk, sn, lat->sparse(), psi, psi, g, lat->ph, odd, s2);
             }
         }
         HIP_TRY(hipGetLastError());
