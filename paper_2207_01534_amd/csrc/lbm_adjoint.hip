@@ -261,15 +261,30 @@ __global__ __launch_bounds__(256) void k_adj_seed(Pops<CF> P, const int* __restr
     rbar[kf] = r;
 }
 
+// Neighbour fluid ids of every fluid node, by fluid id: nfid[(i-1) np + k] =
+// fluid id of x(k) + e_i, -1 where that node is solid.  Built once per
+// gradient call, so that the reverse collide reads a node's neighbour ids as
+// 18 coalesced loads that depend on nothing, instead of gathering them from
+// the lattice map after its own lattice index has arrived.
+__global__ __launch_bounds__(256) void k_adj_neighbours(const int* __restrict__ node_of, int nfluid,
+                                                        const int* __restrict__ fid, Geo g, int* __restrict__ nfid) {
+    const int kf = xcd_item(nfluid);
+    if (kf < 0) return;
+    const int idx = node_of[kf];
+    const Nb nb(idx % g.nx, (idx / g.nx) % g.ny, idx / (g.nx * g.ny), g);
+    const size_t np = (size_t)g.np;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) nfid[(size_t)(i - 1) * np + kf] = fid[nb.at(i, +1)];
+}
+
 // ---------------------------------------------------------------------------
 // A1: adjoint of streaming and of the local collision at fluid nodes.
 // ---------------------------------------------------------------------------
 // One thread per fluid node, in fluid-id order (node_of: fluid id -> lattice
 // index); Abar stays zero at solid nodes (cleared once per gradient call).
 template <bool ODD>
-__global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __restrict__ fid,
+__global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __restrict__ nfid,
                                                      const int* __restrict__ node_of, int nfluid,
-                                                     const uint32_t* __restrict__ nbm,
                                                      const float2* __restrict__ psi,
                                                      const float* __restrict__ lam_next,
                                                      const float2* __restrict__ rbar_next,
@@ -281,10 +296,11 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
     const int x = idx % g.nx, y = (idx / g.nx) % g.ny, z = idx / (g.nx * g.ny);
     const Nb nb(x, y, z, g);
     const size_t n = (size_t)g.n, np = (size_t)g.np;
-    const uint32_t m = nbm[nb.idx];
+    // fluid id of x + s e_i (-1 at solid): x - e_i is x + e_opp(i)
+    auto nf = [&](int i, int s) { return nfid[(size_t)((s > 0 ? i : opp(i)) - 1) * np + kf]; };
     // forward quantities of this node at time t
     float f[2][Q];
-    load_node<CF, ODD>(f, P, nullptr, m, nb, (uint32_t)kf, [&](int i, int s) { return fid[nb.at(i, s)]; }, g.np, 0.0f);
+    load_node<CF, ODD>(f, P, nullptr, 0u, nb, (uint32_t)kf, nf, g.np, 0.0f);
     const float rho[2] = {sum19(f[0]), sum19(f[1])};
     float A[2][3];
     psi_sum([&](int i) { return ld(psi, nb.at(i, +1)); }, A);
@@ -318,8 +334,9 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pops<CF> P, const int* __re
         ls[1][0] = l0.y + rb0.y;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const bool wall = (m >> i) & 1u;
-            const uint32_t at = wall ? (uint32_t)kf : (uint32_t)fid[nb.at(i, +1)];
+            const int nbf = nf(i, +1);
+            const bool wall = nbf < 0;
+            const uint32_t at = wall ? (uint32_t)kf : (uint32_t)nbf;
             const int dir = wall ? opp(i) : i;
             const float2 rb = rbar_next[at];
             const float2 lv = ln[(size_t)dir * np + at];
@@ -552,17 +569,23 @@ void launch_node_of(const int* fid, const Geo& g, int* node_of, hipStream_t s) {
     hipLaunchKernelGGL(k_node_of, dim3((g.n + 255) / 256), dim3(256), 0, s, fid, g.n, node_of);
 }
 
-void launch_adj_collide(const Pops<CF>& P, const int* fid, const int* node_of, int nfluid, const uint32_t* nbm,
-                        const float2* psi, const float* lam_next, const float2* rbar_next, float* lam_cur,
-                        float* abar, const Geo& g, const Phys& ph, int odd, hipStream_t s) {
+void launch_adj_neighbours(const int* node_of, int nfluid, const int* fid, const Geo& g, int* nfid, hipStream_t s) {
+    if (nfluid <= 0) return;
+    hipLaunchKernelGGL(k_adj_neighbours, dim3(xcd_grid((nfluid + 255) / 256)), dim3(256), 0, s, node_of, nfluid, fid,
+                       g, nfid);
+}
+
+void launch_adj_collide(const Pops<CF>& P, const int* nfid, const int* node_of, int nfluid, const float2* psi,
+                        const float* lam_next, const float2* rbar_next, float* lam_cur, float* abar, const Geo& g,
+                        const Phys& ph, int odd, hipStream_t s) {
     if (nfluid <= 0) return;
     const dim3 grid(xcd_grid((nfluid + 255) / 256));
     if (odd)
-        hipLaunchKernelGGL(k_adj_collide<true>, grid, dim3(256), 0, s, P, fid, node_of, nfluid, nbm, psi, lam_next,
+        hipLaunchKernelGGL(k_adj_collide<true>, grid, dim3(256), 0, s, P, nfid, node_of, nfluid, psi, lam_next,
                            rbar_next, lam_cur, abar, g, ph);
     else
-        hipLaunchKernelGGL(k_adj_collide<false>, grid, dim3(256), 0, s, P, fid, node_of, nfluid, nbm, psi,
-                           lam_next, rbar_next, lam_cur, abar, g, ph);
+        hipLaunchKernelGGL(k_adj_collide<false>, grid, dim3(256), 0, s, P, nfid, node_of, nfluid, psi, lam_next,
+                           rbar_next, lam_cur, abar, g, ph);
 }
 
 void launch_adj_ivsd(const int* list, const float* xil, int count, const uint32_t* nbm, const float2* psi,

@@ -612,6 +612,7 @@ struct AdjointWork {
     float2* nbar;
     double* gacc;   // per boundary-list entry
     int* node_of;   // lattice index of each fluid id
+    int* nfid;      // [18][np] neighbour fluid ids of each fluid id (-1 at solid)
     size_t total;
 };
 
@@ -637,6 +638,7 @@ static AdjointWork adjoint_layout(const mclbm_lattice* lat, int32_t every, char*
     w.nbar = (float2*)take(n * sizeof(float2));
     w.gacc = (double*)take(n * sizeof(double));
     w.node_of = (int*)take((size_t)lat->L.cap * sizeof(int));
+    w.nfid = (int*)take((size_t)(Q - 1) * np * sizeof(int));
     w.total = off;
     return w;
 }
@@ -734,6 +736,7 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
     launch_zero(W.gacc, (size_t)lat->nbound * sizeof(double), s);
     launch_zero(W.abar, 6 * n * sizeof(float), s);  // solid entries are never written by the reverse steps
     launch_node_of(lat->fid(), g, W.node_of, s);
+    launch_adj_neighbours(W.node_of, lat->nfluid, lat->fid(), g, W.nfid, s);
     launch_zero(d_grad_xi, n * sizeof(double), s);
     // seed from the final state (the lattice's current populations)
     int cur = 0;  // lam[cur], rbar[cur] hold dL/df at the time level being processed
@@ -815,8 +818,8 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
             const Pops<CodecF32> sk = slot_pops(W.seg[b] + (size_t)k * slot, L);
             const float2* psi = (const float2*)(W.psi[b] + (size_t)k * psi_stride);
             const int nxt = cur, now = 1 - cur;
-            launch_adj_collide(sk, lat->fid(), W.node_of, lat->nfluid, lat->nbm(), psi, W.lam[nxt], W.rbar[nxt],
-                               W.lam[now], W.abar, g, lat->ph, odd, s);
+            launch_adj_collide(sk, W.nfid, W.node_of, lat->nfluid, psi, W.lam[nxt], W.rbar[nxt], W.lam[now], W.abar, g,
+                               lat->ph, odd, s);
             launch_adj_ivsd(lat->list(), lat->xil(), lat->nbound, lat->nbm(), psi, W.abar, g, W.gacc, W.nbar, s);
             launch_adj_rho(W.node_of, lat->nfluid, lat->nbm(), W.abar, W.nbar, g, W.rbar[now], s);
             cur = now;
