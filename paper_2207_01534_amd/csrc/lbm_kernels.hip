@@ -394,7 +394,15 @@ void k_density(Pops<C> P, Sparse S, const float2* __restrict__ rprev, float2* __
     const int j0 = threadIdx.x;
     const uint16_t loc0 = (C::kRef && j0 < count) ? S.loc[base + j0] : (uint16_t)0;
     if constexpr (ODD) {
-        stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
+        // odd levels: the codec's previous-level halo (F16/BF16) is staged with
+        // the fluid-id halo the gathers need, under one wait and one barrier
+        const HaloSlots hs(x0, y0, z0, g);
+        int vf[HaloSlots::RPW], vft;
+        float2 vr[HaloSlots::RPW], vrt;
+        hs.gather([&](uint32_t i) { return S.fid[i]; }, -1, vf, vft);
+        if constexpr (C::kRef) hs.gather([&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f), vr, vrt);
+        hs.put(fidt, vf, vft);
+        if constexpr (C::kRef) hs.put(reft, vr, vrt);
         __syncthreads();
     }
     // the F16/BF16 decoders also need the node's neighbourhood word (by fluid
@@ -422,7 +430,7 @@ void k_density(Pops<C> P, Sparse S, const float2* __restrict__ rprev, float2* __
     TilePos q(0);
     uint32_t m = 0u;
     if (j0 < count) fetch(j0, loc0, r, q, m);
-    if constexpr (C::kRef) {
+    if constexpr (C::kRef && !ODD) {
         stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
         __syncthreads();
     }
@@ -505,11 +513,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
     // slower for FP32, whose kernels load it in fetch)
     const int j0 = threadIdx.x;
     const uint16_t loc0 = (C::kRef && j0 < count) ? S.loc[base + j0] : (uint16_t)0;
+    __shared__ float2 reft[C::kRef ? HZ : 1][HY][HX];
     if constexpr (ODD) {
-        stage_halo(fidt, x0, y0, z0, g, [&](uint32_t i) { return S.fid[i]; }, -1);
+        // odd levels: the psi-hat halos are staged with the fluid-id halo the
+        // gathers need, under one wait and one barrier
+        const HaloSlots hs(x0, y0, z0, g);
+        int vf[HaloSlots::RPW], vft;
+        float2 vp[HaloSlots::RPW], vpt, vr[HaloSlots::RPW], vrt;
+        hs.gather([&](uint32_t i) { return S.fid[i]; }, -1, vf, vft);
+        hs.gather([&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f), vp, vpt);
+        if constexpr (C::kRef) hs.gather([&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f), vr, vrt);
+        hs.put(fidt, vf, vft);
+        hs.put(psit, vp, vpt);
+        if constexpr (C::kRef) hs.put(reft, vr, vrt);
         __syncthreads();
     }
-    __shared__ float2 reft[C::kRef ? HZ : 1][HY][HX];
     // the F16/BF16 codecs also need the node's neighbourhood word (by fluid
     // id, so coalesced and with no lookup before it); it is requested with the
     // populations, not after the wait for them
@@ -552,12 +570,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
     HaloFid h;
     uint32_t m = 0u;
     if (j0 < count) fetch(j0, loc0, r, h, m);
-    if constexpr (C::kRef)
-        stage_halo2(psit, [&](uint32_t i) { return ld(psi, i); }, reft, [&](uint32_t i) { return ld(rprev, i); }, x0,
-                    y0, z0, g, make_float2(0.f, 0.f));
-    else
-        stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
-    __syncthreads();
+    if constexpr (!ODD) {
+        if constexpr (C::kRef)
+            stage_halo2(psit, [&](uint32_t i) { return ld(psi, i); }, reft, [&](uint32_t i) { return ld(rprev, i); },
+                        x0, y0, z0, g, make_float2(0.f, 0.f));
+        else
+            stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
+        __syncthreads();
+    }
     if (j0 < count) finish(j0, r, h, m);
     for (int j = j0 + NT; j < count; j += NT) {
         fetch(j, C::kRef ? S.loc[base + j] : (uint16_t)0, r, h, m);
