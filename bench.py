@@ -140,8 +140,13 @@ def adjoint_cases():
 def run_adjoint(label, w, rho0, region, steps=500, every=25):
     """Adjoint cost of one case: forward, forward with checkpoints, and the
     reverse sweep (segment recompute included), median of three after one
-    untimed pass of each.  region None: the trapped non-wetting region of the
-    unperturbed forward run (workloads.trapped_region), then frozen."""
+    untimed pass of each.  The checkpoint buffer also holds the level log
+    (every level's pseudopotential field and the last segment's states), so
+    that the segment recompute runs the collide-stream kernel only and skips
+    the last segment; the same sweep without the log is timed too, and the
+    two gradients compared bit for bit.  region None: the
+    trapped non-wetting region of the unperturbed forward run
+    (workloads.trapped_region), then frozen."""
     import torch
     from paper_2207_01534_amd import workloads as wl
     from paper_2207_01534_amd.lattice import Lattice, LatticeParams
@@ -165,9 +170,9 @@ def run_adjoint(label, w, rho0, region, steps=500, every=25):
         lat.init_equilibrium(rho)
         return lat.step(steps)
 
-    def forward_checkpointed():
+    def forward_checkpointed(level_log=True):
         lat.init_equilibrium(rho)
-        return lat.step_checkpointed(steps, every)
+        return lat.step_checkpointed(steps, every, level_log=level_log)
 
     # warm-up: one pass of each timed operation (clocks, code objects, work buffer)
     forward()
@@ -180,11 +185,19 @@ def run_adjoint(label, w, rho0, region, steps=500, every=25):
     _, t_fwd_ck = median_of(forward_checkpointed)
     ck = forward_checkpointed()  # the reverse sweep differentiates the latest recording
     grad, t_bwd = median_of(lambda: lat.gradient_snw(steps, every, ck, reg))
+    # the same without the level log: the recompute also forms each level's psi-hat
+    del ck
+    ck = forward_checkpointed(level_log=False)
+    lat.gradient_snw(steps, every, ck, reg)
+    grad0, t_bwd0 = median_of(lambda: lat.gradient_snw(steps, every, ck, reg))
     out = {"workload": label, "steps": steps, "every": every, "region_voxels": int(region.sum()),
            "forward_ms": t_fwd * 1e3, "forward_checkpointed_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
            "cost_ratio": t_bwd / t_fwd, "cost_ratio_vs_checkpointed": t_bwd / t_fwd_ck,
+           "level_log": True, "backward_without_level_log_ms": t_bwd0 * 1e3,
+           "cost_ratio_without_level_log": t_bwd0 / t_fwd,
+           "gradients_bitwise_equal": bool(torch.equal(grad, grad0)),
            "boundary_voxels": lat.boundary_count(), "grad_abs_max": float(grad.abs().max())}
-    del lat, ck, grad
+    del lat, ck, grad, grad0
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return out

@@ -242,24 +242,41 @@ mclbm_status mclbm_loss_flux(mclbm_lattice* lat, const uint8_t* d_region, double
  * steps: ceil(nsteps/every) population states. */
 mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes);
 
-/* Bytes of the work buffer mclbm_gradient_snw needs: two buffers of `every`
- * recomputed states and psi-hat fields (one segment is recomputed while the
+/* Bytes of a checkpoint buffer that also holds the level log: after the
+ * mclbm_checkpoint_bytes of checkpoints (rounded up to 256 bytes), the
+ * pseudopotential field psi-hat (Eqs. 3, 14-15: N component pairs, each
+ * field rounded up to 256 bytes) of each of the nsteps levels, then the
+ * states of the last segment's levels after its first.  Given a buffer at
+ * least this large, mclbm_step_checkpointed writes each level's psi-hat
+ * into the log as it computes it and steps the last segment out of place
+ * through its slots (the same kernels and bytes as mclbm_step), and the
+ * reverse sweep then recomputes the other segments' states with the
+ * collide-stream kernel alone and the last segment not at all. */
+mclbm_status mclbm_checkpoint_bytes_log(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes);
+
+/* Bytes of the work buffer mclbm_gradient_snw needs: two buffers of
+ * `every` - 1 recomputed states (a segment's first state is read from its
+ * checkpoint) and `every` psi-hat fields (one segment is recomputed while the
  * next is reversed) plus the adjoint fields. */
 mclbm_status mclbm_adjoint_work_bytes(const mclbm_lattice* lat, int32_t every, size_t* bytes);
 
 /* mclbm_step(nsteps) that also copies the state into slot k of d_ckpt
  * before step k*every (k = 0, 1, ...).  d_ckpt: device, 256-byte aligned,
- * >= mclbm_checkpoint_bytes. */
+ * >= mclbm_checkpoint_bytes.  With bytes >= mclbm_checkpoint_bytes_log it
+ * also keeps the level log there; the lattice's state and fields are left
+ * as mclbm_step leaves them either way. */
 mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t every, void* d_ckpt,
                                      size_t bytes);
 
 /* Reverse sweep: dL/dxi for the loss at the current time level, through the
  * nsteps steps recorded by the last mclbm_step_checkpointed on this lattice:
  * d_ckpt, nsteps and every must be that call's (EINVAL otherwise), ckpt_bytes
- * the size of d_ckpt (EINVAL below mclbm_checkpoint_bytes), and nothing may
- * have changed the state since -- a step, init_equilibrium, load_state,
+ * the size of d_ckpt (EINVAL below mclbm_checkpoint_bytes, or below
+ * mclbm_checkpoint_bytes_log when the recording kept the level log), and
+ * nothing may have changed the state since -- a step, init_equilibrium, load_state,
  * set_geometry or set_open_x (ESTATE otherwise).  Each segment of `every`
- * steps is recomputed from its checkpoint into d_work, then the adjoint
+ * steps is recomputed from its checkpoint into d_work (its states only with
+ * the level log, which also holds the last segment), then the adjoint
  * steps run backwards through it (adjoint of streaming with bounce-back,
  * of the forced collision, Eqs. 1-2, 6-9, and of the forces and virtual
  * solid densities, Eqs. 10-15).  d_grad_xi: double[N] (output; written in

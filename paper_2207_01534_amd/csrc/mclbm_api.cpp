@@ -135,6 +135,7 @@ struct mclbm_lattice {
         const void* ckpt;
         size_t bytes;
         int32_t nsteps, every;
+        bool level_log;       // the level log kept after the checkpoints
         bool valid;
     } record{};
     // open inlet/outlet planes along x (lbm_open.hip)
@@ -603,8 +604,36 @@ mclbm_status mclbm_checkpoint_bytes(const mclbm_lattice* lat, int32_t nsteps, in
     return MCLBM_OK;
 }
 
+// One psi-hat field (N component pairs) of the checkpoint buffer's level log.
+static size_t psi_field_bytes(const Geo& g) { return align_up((size_t)g.n * sizeof(float2), kAlign); }
+
+// A checkpoint buffer with the level log: the checkpoints, then the psi-hat
+// field of every level (offset psi), then the states of the last segment
+// after its first, which is its checkpoint (offset tail, tail_slots slots).
+struct LevelLog {
+    size_t psi, tail, total;
+    int tail_slots;
+};
+
+static LevelLog level_log_layout(const mclbm_lattice* lat, int32_t nsteps, int32_t every) {
+    size_t states = 0;
+    mclbm_checkpoint_bytes(lat, nsteps, every, &states);
+    LevelLog o;
+    o.psi = align_up(states, kAlign);
+    o.tail = o.psi + (size_t)nsteps * psi_field_bytes(lat->g);
+    o.tail_slots = nsteps - (nsteps - 1) / every * every - 1;  // the last segment's length - 1
+    o.total = o.tail + (size_t)o.tail_slots * state_slot_bytes(lat->L);
+    return o;
+}
+
+mclbm_status mclbm_checkpoint_bytes_log(const mclbm_lattice* lat, int32_t nsteps, int32_t every, size_t* bytes) {
+    if (!lat || !bytes || nsteps < 1 || every < 1) return fail(MCLBM_EINVAL, "bad argument");
+    *bytes = level_log_layout(lat, nsteps, every).total;
+    return MCLBM_OK;
+}
+
 struct AdjointWork {
-    char* seg[2];   // two segment buffers of `every` state slots
+    char* seg[2];   // two segment buffers of `every` - 1 state slots (a segment's first state is its checkpoint)
     char* psi[2];   // and of `every` psi-hat fields (n float2 each)
     float* lam[2];   // [19][np] component pairs, by fluid id
     float* abar;     // [3][n] pairs (component 1, component 2), by lattice node (read at solid neighbours)
@@ -626,7 +655,7 @@ static AdjointWork adjoint_layout(const mclbm_lattice* lat, int32_t every, char*
     };
     AdjointWork w;
     for (int b = 0; b < 2; ++b) {
-        w.seg[b] = take((size_t)every * state_slot_bytes(lat->L));
+        w.seg[b] = take((size_t)(every - 1) * state_slot_bytes(lat->L));
         w.psi[b] = take((size_t)every * align_up(n * sizeof(float2), kAlign));
     }
     const size_t np = (size_t)lat->L.np;  // the adjoint of the populations is indexed by fluid id
@@ -660,21 +689,52 @@ mclbm_status mclbm_step_checkpointed(mclbm_lattice* lat, int32_t nsteps, int32_t
     mclbm_checkpoint_bytes(lat, nsteps, every, &need);
     if (bytes < need) return fail(MCLBM_EINVAL, "checkpoint buffer too small");
     const Layout& L = lat->L;
+    const Geo& g = lat->g;
+    hipStream_t s = lat->stream;
+    // With room for the level log, each level's psi-hat is written there (the
+    // same kernels and bytes as mclbm_step), and the levels of the last
+    // segment run out of place through its slots, so that the reverse sweep
+    // recomputes neither.  The last two levels' psi-hat still goes through
+    // the lattice's own fields, which are left as mclbm_step leaves them, as
+    // is the state.  Solid nodes without a fluid neighbour keep whatever the
+    // log held: no kernel reads psi-hat there.
+    const LevelLog LL = level_log_layout(lat, nsteps, every);
+    const bool level_log = bytes >= LL.total;
+    const int k_last = (nsteps - 1) / every * every;  // first level of the last segment
+    const Pops<CodecF32> P = lat->pops<CodecF32>();
+    auto tail = [&](int j) { return slot_pops((char*)d_ckpt + LL.tail + (size_t)j * state_slot_bytes(L), L); };
     for (int32_t k = 0; k < nsteps; ++k) {
         if (k % every == 0) {
             char* slot = (char*)d_ckpt + (size_t)(k / every) * state_slot_bytes(L);
             const Pops<CodecF32> d = slot_pops(slot, L);
-            HIP_TRY(hipMemcpyAsync(d.mv, lat->ws + L.mv, L.mv_bytes, hipMemcpyDeviceToDevice, lat->stream));
-            HIP_TRY(hipMemcpyAsync(d.rest, lat->ws + L.rest, L.rest_bytes, hipMemcpyDeviceToDevice, lat->stream));
+            HIP_TRY(hipMemcpyAsync(d.mv, lat->ws + L.mv, L.mv_bytes, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(d.rest, lat->ws + L.rest, L.rest_bytes, hipMemcpyDeviceToDevice, s));
         }
-        mclbm_status st = mclbm_step(lat, 1);
-        if (st != MCLBM_OK) return st;
+        if (!level_log) {
+            mclbm_status st = mclbm_step(lat, 1);
+            if (st != MCLBM_OK) return st;
+            continue;
+        }
+        const int odd = (int)(lat->t & 1);
+        float2* logged = (float2*)((char*)d_ckpt + LL.psi + (size_t)k * psi_field_bytes(g));
+        float2* psi = k + 2 >= nsteps ? lat->R(odd) : logged;
+        const Pops<CodecF32> src = k <= k_last ? P : tail(k - k_last - 1);
+        const Pops<CodecF32> dst = (k < k_last || k + 1 == nsteps) ? P : tail(k - k_last);
+        launch_density<CodecF32>(src, lat->sparse(), lat->R(0) /* not read for FP32 */, psi, g, lat->ph.G, odd, s);
+        launch_ivsd(lat->list(), lat->xil(), lat->nbl(), lat->nbound, psi, g, s);
+        launch_collide_stream<CodecF32>(src, dst, lat->sparse(), psi, psi, g, lat->ph, odd, s);
+        HIP_TRY(hipGetLastError());
+        if (psi != logged)
+            HIP_TRY(hipMemcpyAsync(logged, psi, (size_t)g.n * sizeof(float2), hipMemcpyDeviceToDevice, s));
+        lat->t += 1;
+        lat->generation += 1;
     }
     lat->record.generation = lat->generation;
     lat->record.ckpt = d_ckpt;
     lat->record.bytes = bytes;
     lat->record.nsteps = nsteps;
     lat->record.every = every;
+    lat->record.level_log = level_log;
     lat->record.valid = true;
     return MCLBM_OK;
 }
@@ -722,16 +782,34 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
                                   "(the lattice was stepped, re-initialised or reloaded since)");
     if (lat->record.ckpt != d_ckpt || lat->record.nsteps != nsteps || lat->record.every != every)
         return fail(MCLBM_EINVAL, "checkpoints, nsteps or every differ from the last step_checkpointed");
+    const bool level_log = lat->record.level_log;
+    const LevelLog LL = level_log_layout(lat, nsteps, every);
+    if (level_log && ckpt_bytes < LL.total)
+        return fail(MCLBM_EINVAL, "checkpoint buffer smaller than the level log it was recorded with");
     const AdjointWork W = adjoint_layout(lat, every, (char*)d_work);
     if (work_bytes < W.total) return fail(MCLBM_EINVAL, "work buffer too small");
     const Layout& L = lat->L;
     const Geo& g = lat->g;
     const size_t n = (size_t)g.n;
     const size_t slot = state_slot_bytes(L);
-    const size_t psi_stride = align_up(n * sizeof(float2), kAlign);
+    const size_t psi_stride = psi_field_bytes(g);
     hipStream_t s = lat->stream;
     const int64_t t_end = lat->t, t0 = t_end - nsteps;
     const int nseg = (nsteps + every - 1) / every;
+    // state of level k of segment seg: the first is the checkpoint itself
+    // (which every kernel here only reads), the others are recomputed into
+    // buffer b or, for the last segment, kept by the level log
+    auto level_pops = [&](int seg, int b, int k) {
+        if (k == 0) return slot_pops((char*)d_ckpt + (size_t)seg * slot, L);
+        if (level_log && seg == nseg - 1) return slot_pops((char*)d_ckpt + LL.tail + (size_t)(k - 1) * slot, L);
+        return slot_pops(W.seg[b] + (size_t)(k - 1) * slot, L);
+    };
+    // psi-hat of level k of segment seg: from the level log, or recomputed
+    // into buffer b
+    auto level_psi = [&](int seg, int b, int k) {
+        return level_log ? (float2*)((char*)d_ckpt + LL.psi + (size_t)(seg * every + k) * psi_stride)
+                         : (float2*)(W.psi[b] + (size_t)k * psi_stride);
+    };
 
     launch_zero(W.gacc, (size_t)lat->nbound * sizeof(double), s);
     launch_zero(W.abar, 6 * n * sizeof(float), s);  // solid entries are never written by the reverse steps
@@ -779,22 +857,20 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
         const int b = seg & 1;
         const int64_t ta = t0 + (int64_t)seg * every;
         const int len = (int)((ta + every <= t_end ? ta + every : t_end) - ta);
-        const Pops<CodecF32> c = slot_pops((char*)d_ckpt + (size_t)seg * slot, L);
-        const Pops<CodecF32> s0 = slot_pops(W.seg[b], L);
-        HIP_TRY(hipMemcpyAsync(s0.mv, c.mv, L.mv_bytes, hipMemcpyDeviceToDevice, s2));
-        HIP_TRY(hipMemcpyAsync(s0.rest, c.rest, L.rest_bytes, hipMemcpyDeviceToDevice, s2));
-        // the segment's states and their psi-hat fields
-        for (int k = 0; k < len; ++k) {
+        // the segment's states (and their psi-hat fields when there is no
+        // level log, which also holds the last segment's states)
+        for (int k = 0; k < len && !(level_log && seg == nseg - 1); ++k) {
             const int odd = (int)((ta + k) & 1);
-            const Pops<CodecF32> sk = slot_pops(W.seg[b] + (size_t)k * slot, L);
-            float2* psi = (float2*)(W.psi[b] + (size_t)k * psi_stride);
-            launch_density<CodecF32>(sk, lat->sparse(), lat->R(0) /* not read for FP32 */, psi, g, lat->ph.G, odd,
-                                     s2);
-            launch_ivsd(lat->list(), lat->xil(), lat->nbl(), lat->nbound, psi, g, s2);
-            if (k + 1 < len) {
-                const Pops<CodecF32> sn = slot_pops(W.seg[b] + (size_t)(k + 1) * slot, L);
-                launch_collide_stream<CodecF32>(sk, sn, lat->sparse(), psi, psi, g, lat->ph, odd, s2);
+            const Pops<CodecF32> sk = level_pops(seg, b, k);
+            float2* psi = level_psi(seg, b, k);
+            if (!level_log) {
+                launch_density<CodecF32>(sk, lat->sparse(), lat->R(0) /* not read for FP32 */, psi, g, lat->ph.G,
+                                         odd, s2);
+                launch_ivsd(lat->list(), lat->xil(), lat->nbl(), lat->nbound, psi, g, s2);
             }
+            if (k + 1 < len)
+                launch_collide_stream<CodecF32>(sk, level_pops(seg, b, k + 1), lat->sparse(), psi, psi, g, lat->ph,
+                                                odd, s2);
         }
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(lat->ev_rec[b], s2));
@@ -815,8 +891,8 @@ static mclbm_status gradient(mclbm_lattice* lat, LossKind kind, int32_t nsteps, 
         // reverse steps
         for (int k = len - 1; k >= 0; --k) {
             const int odd = (int)((ta + k) & 1);
-            const Pops<CodecF32> sk = slot_pops(W.seg[b] + (size_t)k * slot, L);
-            const float2* psi = (const float2*)(W.psi[b] + (size_t)k * psi_stride);
+            const Pops<CodecF32> sk = level_pops(seg, b, k);
+            const float2* psi = level_psi(seg, b, k);
             const int nxt = cur, now = 1 - cur;
             launch_adj_collide(sk, W.nfid, W.node_of, lat->nfluid, psi, W.lam[nxt], W.rbar[nxt], W.lam[now], W.abar, g,
                                lat->ph, odd, s);

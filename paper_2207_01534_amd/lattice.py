@@ -69,6 +69,7 @@ SIGNATURES = [
     ("mclbm_loss_snw", _I32, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("mclbm_loss_flux", _I32, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("mclbm_checkpoint_bytes", _I32, [_VP, _I32, _I32, _SZP]),
+    ("mclbm_checkpoint_bytes_log", _I32, [_VP, _I32, _I32, _SZP]),
     ("mclbm_adjoint_work_bytes", _I32, [_VP, _I32, _SZP]),
     ("mclbm_step_checkpointed", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t]),
     ("mclbm_gradient_snw", _I32, [_VP, _I32, _I32, _VP, ctypes.c_size_t, _VP, _VP, ctypes.c_size_t, _VP]),
@@ -259,10 +260,23 @@ class Lattice:
         _check(_lib.mclbm_loss_flux(self._h, _ptr(reg), ctypes.byref(L)), "loss_flux")
         return L.value
 
-    def step_checkpointed(self, nsteps: int, every: int) -> torch.Tensor:
-        """Advance nsteps, keeping a checkpoint every `every` steps; returns the buffer."""
+    def step_checkpointed(self, nsteps: int, every: int, level_log=None) -> torch.Tensor:
+        """Advance nsteps, keeping a checkpoint every `every` steps; returns the buffer.
+
+        level_log: also keep every level's psi-hat (8 bytes per lattice node and
+        step) and the last segment's states, so that the reverse sweep
+        recomputes the other segments' states only.  None keeps it when it takes
+        at most half of the device memory free now."""
         b = ctypes.c_size_t()
         _check(_lib.mclbm_checkpoint_bytes(self._h, int(nsteps), int(every), ctypes.byref(b)), "checkpoint_bytes")
+        full = ctypes.c_size_t()
+        _check(_lib.mclbm_checkpoint_bytes_log(self._h, int(nsteps), int(every), ctypes.byref(full)),
+               "checkpoint_bytes_log")
+        if level_log is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            level_log = full.value <= free // 2
+        if level_log:
+            b = full
         ck = torch.empty(b.value, dtype=torch.uint8, device=self.device)
         _check(_lib.mclbm_step_checkpointed(self._h, int(nsteps), int(every), _ptr(ck), b.value),
                "step_checkpointed")

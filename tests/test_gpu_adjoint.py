@@ -338,3 +338,40 @@ def test_reverse_sweep_refuses_a_state_it_was_not_recorded_for():
         lat.gradient_snw(6, 2, ck_a, reg)                      # superseded by the second recording
     g3 = lat.gradient_snw(6, 2, ck_b, reg)
     assert torch.equal(g1, g3)
+
+
+@pytest.mark.parametrize("steps,every", [(1, 1), (5, 1), (9, 4), (10, 5), (30, 7)])
+def test_level_log_gives_the_same_gradient_bit_for_bit(steps, every):
+    """A checkpoint buffer with the level log (every level's pseudopotential
+    field and the last segment's states, kept by the forward) lets the reverse
+    sweep skip recomputing the densities, the virtual solid densities and the
+    last segment.  Both sweeps must give the same gradient bit for bit, for
+    both losses, with last segments of one to five steps and with one step
+    per segment, and the forward must leave the lattice's state as the plain
+    recording does.  A buffer cut below the log it was recorded with is
+    refused."""
+    import torch
+    from paper_2207_01534_amd.lattice import Lattice, LatticeParams, MclbmError
+    shape = (20, 14, 12)
+    solid = wl.random_mask(shape, 0.3, seed=95)
+    xi = wl.uniform_xi(solid, -0.4, 0.4, seed=96)
+    rho = wl.tanh_droplet(shape, 4.0)
+    rho[:, solid != 0] = 0
+    rho_t = torch.as_tensor(rho.astype(np.float32), device="cuda")
+    lat = Lattice(LatticeParams(shape=shape, tau=(1.5, 0.6), G=3.5, g=((1e-5, 0, 0), (0, 0, 0))),
+                  torch.as_tensor(solid), torch.as_tensor(xi), rho_t)
+    reg = torch.zeros(shape[::-1], dtype=torch.uint8, device="cuda")
+    reg[:, :, shape[0] // 2:] = 1
+    out = {}
+    for log in (False, True):
+        lat.init_equilibrium(rho_t)
+        ck = lat.step_checkpointed(steps, every, level_log=log)
+        state = lat.save(torch.zeros(lat.state_bytes(), dtype=torch.uint8, device="cuda"))  # padding zeroed
+        out[log] = (lat.gradient_snw(steps, every, ck, reg), lat.gradient_flux(steps, every, ck, reg), state)
+        if log:
+            with pytest.raises(MclbmError):
+                lat.gradient_snw(steps, every, ck[: ck.numel() - 256], reg)
+    assert torch.equal(out[True][0], out[False][0])
+    assert torch.equal(out[True][1], out[False][1])
+    assert torch.equal(out[True][2], out[False][2])
+    assert float(out[True][0].abs().max()) > 0 and float(out[True][1].abs().max()) > 0
