@@ -279,7 +279,9 @@ __global__ void k_init(Pops<C> P, const uint32_t* __restrict__ nbm, const int* _
 // issues the loads of one field, put() writes them to LDS, and every gather
 // of a thread comes before its first put, so all of its loads (and any the
 // caller issued before) are in flight together: each put waits for the
-// thread's loads in issue order.
+// thread's loads in issue order.  direct() loads the same rows straight into
+// LDS instead (no registers, no LDS writes by the waves), where every halo
+// position lies inside the lattice after one wrap.
 struct HaloSlots {
     static constexpr int NW = NT / 64;
     static constexpr int RPW = (HZ * HY + NW - 1) / NW;  // rows per wave (the last ones may run past HZ*HY)
@@ -324,6 +326,36 @@ struct HaloSlots {
         vt = fill;
         if (has_tail && okt && gxt < g.nx) vt = src(rbt + (uint32_t)gxt);
     }
+    // every halo position inside the lattice after one wrap: no fill values
+    __host__ __device__ static bool direct_ok(const Geo& g) { return g.nx >= TX && g.ny >= TY && g.nz >= TZ; }
+    // Rows of 4- or 8-byte elements loaded with global_load_lds: lane l's
+    // dword lands at the instruction's LDS address + 4 l, so each instruction
+    // fills 64 consecutive dwords of a row (an 8-byte element takes two
+    // lanes).  The caller waits for the loads (vmcnt) before the barrier.
+    template <class T>
+    __device__ __forceinline__ void direct(T (*tile)[HY][HX], const T* src) const {
+        constexpr int W = (int)(sizeof(T) / 4);  // dwords per element
+        static_assert(HZ * HY == NW * RPW, "whole rows per wave");
+#pragma unroll
+        for (int p = 0; p < RPW; ++p) {
+            const int r = wave + NW * p;
+            bool ok;
+            const uint32_t rb = row_base(r, ok);
+            char* lrow = (char*)&tile[r / HY][r % HY][0];
+#pragma unroll
+            for (int k = 0; k < (HX * W + 63) / 64; ++k) {
+                const int d = 64 * k + lane;  // dword of the row
+                const int pos = d / W, c = d - pos * W;
+                int x = x0 - 1 + pos;
+                x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+                if (d < HX * W)
+                    __builtin_amdgcn_global_load_lds(
+                        (__attribute__((address_space(1))) void*)((const char*)src +
+                                                                  ((size_t)(rb + (uint32_t)x) * W + c) * 4),
+                        (__attribute__((address_space(3))) void*)(lrow + 256 * k), 4, 0, 0);
+            }
+        }
+    }
     template <class T>
     __device__ __forceinline__ void put(T (*tile)[HY][HX], const T (&v)[RPW], T vt) const {
 #pragma unroll
@@ -335,6 +367,10 @@ struct HaloSlots {
         if (has_tail && rt < HZ * HY) tile[rt / HY][rt % HY][64 + (lane & 1)] = vt;
     }
 };
+
+// wait for this wave's outstanding vector memory loads (vmcnt(0); the
+// expcnt and lgkmcnt fields at their maxima), direct() loads included
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }
 
 template <class T, class Src>
 __device__ __forceinline__ void stage_halo(T (*tile)[HY][HX], int x0, int y0, int z0, const Geo& g, Src src,
@@ -376,7 +412,7 @@ struct HaloFid {
 // node is loaded.  At least 8 waves per SIMD in even steps (7 with a
 // decoding halo) and 6 in odd steps; the compiler's default schedule would
 // hold ~105 VGPRs.
-template <class C, bool ODD, bool WIDE>
+template <class C, bool ODD, bool WIDE, bool DIRECT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ODD ? 6 : (C::kRef ? 7 : 8))))
 void k_density(Pops<C> P, Sparse S, const float2* __restrict__ rprev, float2* __restrict__ psi, Geo g, float G) {
     const int a = active_of_block(S.nactive);
@@ -397,12 +433,18 @@ void k_density(Pops<C> P, Sparse S, const float2* __restrict__ rprev, float2* __
         // odd levels: the codec's previous-level halo (F16/BF16) is staged with
         // the fluid-id halo the gathers need, under one wait and one barrier
         const HaloSlots hs(x0, y0, z0, g);
-        int vf[HaloSlots::RPW], vft;
-        float2 vr[HaloSlots::RPW], vrt;
-        hs.gather([&](uint32_t i) { return S.fid[i]; }, -1, vf, vft);
-        if constexpr (C::kRef) hs.gather([&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f), vr, vrt);
-        hs.put(fidt, vf, vft);
-        if constexpr (C::kRef) hs.put(reft, vr, vrt);
+        if constexpr (DIRECT) {
+            hs.direct(fidt, S.fid);
+            if constexpr (C::kRef) hs.direct(reft, rprev);
+            wait_vm();
+        } else {
+            int vf[HaloSlots::RPW], vft;
+            float2 vr[HaloSlots::RPW], vrt;
+            hs.gather([&](uint32_t i) { return S.fid[i]; }, -1, vf, vft);
+            if constexpr (C::kRef) hs.gather([&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f), vr, vrt);
+            hs.put(fidt, vf, vft);
+            if constexpr (C::kRef) hs.put(reft, vr, vrt);
+        }
         __syncthreads();
     }
     // the F16/BF16 decoders also need the node's neighbourhood word (by fluid
@@ -431,7 +473,12 @@ void k_density(Pops<C> P, Sparse S, const float2* __restrict__ rprev, float2* __
     uint32_t m = 0u;
     if (j0 < count) fetch(j0, loc0, r, q, m);
     if constexpr (C::kRef && !ODD) {
-        stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
+        if constexpr (DIRECT) {
+            HaloSlots(x0, y0, z0, g).direct(reft, rprev);
+            wait_vm();
+        } else {
+            stage_halo(reft, x0, y0, z0, g, [&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f));
+        }
         __syncthreads();
     }
     if (j0 < count) finish(r, q, m);
@@ -495,7 +542,7 @@ __global__ __launch_bounds__(256) void k_ivsd(const int* __restrict__ list, cons
 // spill with 32-bit slot offsets); the FP16/BF16 codecs, whose populations
 // take half the registers, run 5 (odd steps spill a few dwords, which costs
 // less than the lost wave).
-template <class C, bool ODD, bool WIDE>
+template <class C, bool ODD, bool WIDE, bool DIRECT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 : 4))) void k_collide_stream(Pops<C> P, Pops<C> D, Sparse S,
                                                        const float2* __restrict__ rprev,
                                                        const float2* __restrict__ psi, Geo g, Phys ph) {
@@ -518,14 +565,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
         // odd levels: the psi-hat halos are staged with the fluid-id halo the
         // gathers need, under one wait and one barrier
         const HaloSlots hs(x0, y0, z0, g);
-        int vf[HaloSlots::RPW], vft;
-        float2 vp[HaloSlots::RPW], vpt, vr[HaloSlots::RPW], vrt;
-        hs.gather([&](uint32_t i) { return S.fid[i]; }, -1, vf, vft);
-        hs.gather([&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f), vp, vpt);
-        if constexpr (C::kRef) hs.gather([&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f), vr, vrt);
-        hs.put(fidt, vf, vft);
-        hs.put(psit, vp, vpt);
-        if constexpr (C::kRef) hs.put(reft, vr, vrt);
+        if constexpr (DIRECT) {
+            hs.direct(fidt, S.fid);
+            hs.direct(psit, psi);
+            if constexpr (C::kRef) hs.direct(reft, rprev);
+            wait_vm();
+        } else {
+            int vf[HaloSlots::RPW], vft;
+            float2 vp[HaloSlots::RPW], vpt, vr[HaloSlots::RPW], vrt;
+            hs.gather([&](uint32_t i) { return S.fid[i]; }, -1, vf, vft);
+            hs.gather([&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f), vp, vpt);
+            if constexpr (C::kRef) hs.gather([&](uint32_t i) { return ld(rprev, i); }, make_float2(0.f, 0.f), vr, vrt);
+            hs.put(fidt, vf, vft);
+            hs.put(psit, vp, vpt);
+            if constexpr (C::kRef) hs.put(reft, vr, vrt);
+        }
         __syncthreads();
     }
     // the F16/BF16 codecs also need the node's neighbourhood word (by fluid
@@ -571,11 +625,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(C::kRef ? 5 
     uint32_t m = 0u;
     if (j0 < count) fetch(j0, loc0, r, h, m);
     if constexpr (!ODD) {
-        if constexpr (C::kRef)
+        if constexpr (DIRECT) {
+            const HaloSlots hs(x0, y0, z0, g);
+            hs.direct(psit, psi);
+            if constexpr (C::kRef) hs.direct(reft, rprev);
+            wait_vm();
+        } else if constexpr (C::kRef) {
             stage_halo2(psit, [&](uint32_t i) { return ld(psi, i); }, reft, [&](uint32_t i) { return ld(rprev, i); },
                         x0, y0, z0, g, make_float2(0.f, 0.f));
-        else
+        } else {
             stage_halo(psit, x0, y0, z0, g, [&](uint32_t i) { return ld(psi, i); }, make_float2(0.f, 0.f));
+        }
         __syncthreads();
     }
     if (j0 < count) finish(j0, r, h, m);
@@ -762,10 +822,16 @@ void launch_init(const Pops<C>& P, const uint32_t* nbm, const int* fid, const fl
     hipLaunchKernelGGL(k_init<C>, row_grid(g), dim3(64), 0, s, P, nbm, fid, (const float2*)rprev, g, G);
 }
 
+// halos loaded straight into LDS wherever no halo position needs a fill value
 template <class C, bool ODD, bool WIDE>
 static void launch_density_as(const Pops<C>& P, const Sparse& S, const float2* rprev, float2* psi, const Geo& g,
                               float G, hipStream_t s) {
-    hipLaunchKernelGGL((k_density<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, rprev, psi, g, G);
+    if (HaloSlots::direct_ok(g))
+        hipLaunchKernelGGL((k_density<C, ODD, WIDE, true>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, rprev,
+                           psi, g, G);
+    else
+        hipLaunchKernelGGL((k_density<C, ODD, WIDE, false>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, S, rprev,
+                           psi, g, G);
 }
 
 template <class C>
@@ -790,8 +856,12 @@ void launch_ivsd(const int* list, const float* xil, const uint32_t* nbl, int cou
 template <class C, bool ODD, bool WIDE>
 static void launch_collide_as(const Pops<C>& P, const Pops<C>& D, const Sparse& S, const float2* rprev,
                               const float2* psi, const Geo& g, const Phys& ph, hipStream_t s) {
-    hipLaunchKernelGGL((k_collide_stream<C, ODD, WIDE>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S, rprev,
-                       psi, g, ph);
+    if (HaloSlots::direct_ok(g))
+        hipLaunchKernelGGL((k_collide_stream<C, ODD, WIDE, true>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D, S,
+                           rprev, psi, g, ph);
+    else
+        hipLaunchKernelGGL((k_collide_stream<C, ODD, WIDE, false>), dim3(xcd_grid(S.nactive)), dim3(NT), 0, s, P, D,
+                           S, rprev, psi, g, ph);
 }
 
 template <class C>
